@@ -1,0 +1,274 @@
+/*
+ * nze.h -- C-ABI of the MI355X (gfx950) library for non-zero noise
+ * extrapolation with vectorised matrix-product operators.
+ *
+ * Reference: A. P. Thompson, A. Soeteman, C. Cade, I. Niesen, "Non-zero noise
+ * extrapolation: accurately simulating noisy quantum circuits with tensor
+ * networks" (arXiv 2501.13237).
+ *
+ * Problem statement the calls follow (Sec. 2.1.2 "Setup", Sec. 2.2.1,
+ * Sec. 2.2.2): a circuit is a sequence of noisy two-qubit gates (subcircuits)
+ * acting on a product initial state; every gate U is followed by a channel C
+ * of a one-parameter noise family (U -> C o U); the state is emulated as a
+ * vectorised MPO of bond dimension at most D ("chi_max" here) at several noise
+ * strengths lambda; Pauli-string expectation values are read out together
+ * with the emulation fidelity, then extrapolated in lambda to a target.
+ *
+ * Conventions shared by every call
+ *  - Status: every call returns 0 on success or a negative NZE_E* code; no
+ *    C++ exception crosses the ABI.  nze_last_error() gives a message for the
+ *    most recent failure on the calling thread.
+ *  - Ownership: the caller owns every host array and the device workspace.
+ *    The library never keeps a caller host pointer past the return of a call.
+ *  - Threads: a handle is not thread-safe; use one handle per host thread.
+ *  - Pauli codes: 0 = I, 1 = X, 2 = Y, 3 = Z.  Two-qubit Pauli index
+ *    P = 4 * p_left + p_right (left = lower site index).
+ *  - Pauli-transfer matrix (PTM) of a two-qubit map E: R[P][Q] =
+ *    Tr(P E(Q)) / 4, row-major 16 x 16, float64.  It acts on Pauli
+ *    coordinates v_P = Tr(P rho).
+ */
+#ifndef NZE_H
+#define NZE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define NZE_OK 0
+#define NZE_EINVAL (-1)   /* bad argument, shape, or unsorted/overlapping sites */
+#define NZE_ENOMEM (-2)   /* workspace too small (also the admission refusal)   */
+#define NZE_EHIP (-3)     /* HIP runtime error                                  */
+#define NZE_ENOCONV (-4)  /* Jacobi SVD reached its sweep cap without converging */
+#define NZE_EFIT (-5)     /* too few admissible points for any extrapolation    */
+#define NZE_ENUM (-6)     /* NaN/Inf met in the state                           */
+
+/* ------------------------------------------------------------- precision */
+#define NZE_FP64 0   /* every contraction and rotation in float64            */
+#define NZE_MIXED 1  /* float32 MFMA contractions/rotations; Jacobi rotation
+                        parameters, truncation decisions, fidelities, norms
+                        and readout in float64                               */
+
+/* ------------------------------------------------------------ fit methods */
+#define NZE_POLY 0      /* least-squares polynomial in lambda                 */
+#define NZE_EXP3 1      /* a exp(-b lambda) + c, unweighted MSE (Sec. 2.2.2 B) */
+#define NZE_LOGLIN_W 2  /* weighted log-linear fit with criteria 2-3, falling
+                           back to NZE_EXP3, then NZE_EFIT (Sec. 2.2.2 B,
+                           App. B.2)                                           */
+
+/* ----------------------------------------------------------------- noise */
+/* One noise family attached after every two-qubit gate (Sec. 2.2.1).  All
+ * parameters are multiplied by the level's scale factor.  Channels are
+ * applied in the order: two-qubit depolarizing (App. C.2.1,
+ * rho -> (1 - dep) rho + dep I/4), amplitude damping with gamma = ad on each
+ * qubit, Pauli channel (px, py, pz) on each qubit. */
+typedef struct nze_noise {
+  double dep;
+  double ad;
+  double px, py, pz;
+} nze_noise;
+
+/* Builds the 16 x 16 PTM of the noisy gate C o U (Sec. 2.2.1: the unitary
+ * acts first, then the channel): R = R_C * R_U with
+ * R_U[P][Q] = Tr(P U Q U^dagger) / 4.
+ *   u_re, u_im : 4 x 4 row-major real and imaginary parts of U (host).  The
+ *                computational-basis index of U is 2 * bit_left + bit_right.
+ *   noise      : channel parameters (host; NULL = noiseless).
+ *   scale      : level factor multiplying every noise parameter.
+ *   ptm_out    : 256 float64, row-major (host, caller-allocated).
+ * Host-only, float64.  Returns NZE_EINVAL on NULL u_re/u_im/ptm_out or on
+ * scaled parameters outside [0, 1]. */
+int nze_build_ptm(const double* u_re, const double* u_im,
+                  const nze_noise* noise, double scale, double* ptm_out);
+
+/* ------------------------------------------------------------ MPO handle */
+typedef struct mpo_handle mpo_t;
+
+typedef struct mpo_config {
+  int32_t n;           /* qubits on the open chain, 2 <= n <= 4096            */
+  int32_t chi_max;     /* maximum bond dimension D (Sec. 2.1.1), 1..1024       */
+  int32_t n_levels;    /* L independent MPOs (one per noise level), >= 1      */
+  int32_t precision;   /* NZE_FP64 or NZE_MIXED                               */
+  double trunc_tol;    /* tau: drop s_i <= tau * s_1 (numerical zeros);
+                          0 -> 1e-14 (FP64) / 1e-7 (mixed)                   */
+  double tie_tol;      /* relative tie tolerance at a chi cut (a tied cluster
+                          is dropped whole); 0 -> 1e-10 (FP64) / 1e-5 (mixed)*/
+  double jacobi_tol;   /* off-diagonal convergence threshold of the one-sided
+                          Jacobi SVD; 0 -> 1e-13 (FP64) / 2e-6 (mixed)        */
+  int32_t max_sweeps;  /* Jacobi sweep cap; 0 -> 20 (FP64) / 14 (mixed)       */
+  int32_t block;       /* Jacobi row-block width b (pairs are 2b rows);
+                          0 -> chosen by the built-in tuner                   */
+} mpo_config;
+
+/* Device bytes the workspace of mpo_init must hold for cfg (0 if cfg is
+ * invalid).  Also the footprint used for admission by HBM budget. */
+size_t mpo_footprint(const mpo_config* cfg);
+
+/* Creates L = cfg->n_levels MPOs in the same product state.
+ *   out        : receives the handle (host).
+ *   init_sites : n x 4 float64 Pauli coordinates (Tr(rho_k), Tr(X rho_k),
+ *                Tr(Y rho_k), Tr(Z rho_k)) of the product state's sites
+ *                (host), or NULL for |0...0> (each site (1, 0, 0, 1)).  The
+ *                initial state is a product state (Sec. 2.1.2).
+ *   workspace  : device memory of at least mpo_footprint(cfg) bytes, 256-byte
+ *                aligned, owned by the caller and kept alive until mpo_free.
+ *   stream     : hipStream_t on which all work of this handle is enqueued
+ *                (NULL = the default stream).
+ * Errors: NZE_EINVAL (bad cfg), NZE_ENOMEM (ws_bytes too small), NZE_EHIP. */
+int mpo_init(mpo_t** out, const mpo_config* cfg, const double* init_sites,
+             void* workspace, size_t ws_bytes, void* stream);
+
+/* Releases the handle's host-side resources (not the caller's workspace).
+ * Synchronises the handle's stream first.  NULL is a no-op. */
+void mpo_free(mpo_t* h);
+
+/* Applies one layer of noisy two-qubit gates to every level
+ * (Sec. 2.1.2 "Approximate emulation"): for each gate the orthogonality
+ * centre is moved next to it, the two site tensors are contracted, the PTM is
+ * applied, the block is split by a truncated SVD to at most chi_max (the
+ * closest fixed-bond-dimension state, renormalised to Frobenius norm 1), and
+ * the partial fidelity (sum of kept s^2 / sum of all s^2) multiplies the
+ * level's emulation fidelity (eq. emulation_fidelity).
+ *   n_gates   : gates in the layer (>= 0).
+ *   left_site : n_gates strictly increasing left sites; gate i acts on
+ *               (left_site[i], left_site[i] + 1); pairs must be disjoint.
+ *               Gates run in increasing order when left_site[0] is even and
+ *               in decreasing order when it is odd (zig-zag sweep).
+ *   ptm       : [n_levels][n_gates][16][16] float64 PTMs (host).
+ * Asynchronous: returns once the inputs are staged; the work runs on the
+ * handle's stream.  A Jacobi non-convergence or NaN is reported by the next
+ * mpo_expect / mpo_stats / mpo_sync.  Errors: NZE_EINVAL, NZE_EHIP. */
+int mpo_apply_layer(mpo_t* h, int32_t n_gates, const int32_t* left_site,
+                    const double* ptm);
+
+/* Several handles advanced by one layer each in the same device launches
+ * (continuous batching of independent jobs).  All handles must share the
+ * precision and the stream of hs[0]; arrays are indexed by handle.
+ * Errors as mpo_apply_layer. */
+int mpo_apply_layer_batch(mpo_t* const* hs, int32_t k, const int32_t* n_gates,
+                          const int32_t* const* left_site,
+                          const double* const* ptm);
+
+/* Reads Pauli-string expectation values at every level.
+ *   n_obs    : number of strings.
+ *   paulis   : [n_obs][n] uint8 Pauli codes (host).
+ *   values   : [n_levels][n_obs] float64 out: <P> = Tr(P rho) / Tr(rho)
+ *              (trace-normalised, Sec. 2.1.2 footnote on normalisation).
+ *   fidelity : [n_levels] float64 out, emulation fidelity (may be NULL).
+ *   trace    : [n_levels] float64 out, Tr(rho) of the emulated (truncated,
+ *              un-renormalised) state; 1 while nothing is truncated (NULL ok).
+ * Synchronises the stream.  Errors: NZE_EINVAL, NZE_EHIP, NZE_ENOCONV,
+ * NZE_ENUM (earlier asynchronous failures are reported here). */
+int mpo_expect(mpo_t* h, int32_t n_obs, const uint8_t* paulis, double* values,
+               double* fidelity, double* trace);
+
+typedef struct nze_stats {
+  double fidelity;       /* emulation fidelity                               */
+  double log_scale;      /* log of the factor removed by renormalisation      */
+  double max_discarded;  /* max over gates of 1 - f                           */
+  double min_cut_gap;    /* min over chi cuts of (s_r - s_{r+1}) / s_1        */
+  int32_t max_bond;      /* largest current bond dimension                    */
+  int32_t max_sweeps;    /* most Jacobi sweeps any SVD needed                 */
+  int64_t updates;       /* two-site updates applied so far                   */
+  int64_t sweeps_total;  /* Jacobi sweeps over all updates and centre moves   */
+} nze_stats;
+
+/* Per-level statistics (synchronises the stream).
+ *   stats : [n_levels] out.   bonds : [n_levels][n-1] int32 out or NULL. */
+int mpo_stats(mpo_t* h, nze_stats* stats, int32_t* bonds);
+
+/* Schmidt values across bond (l, l+1) of level lv (App. A.1: canonical form
+ * at that bond; used for the MPO entanglement entropy).
+ *   s_out : capacity cap float64 (host); *count receives the number written.
+ * Synchronises; moves the orthogonality centre of level lv only. */
+int mpo_bond_spectrum(mpo_t* h, int32_t lv, int32_t l, double* s_out,
+                      int32_t cap, int32_t* count);
+
+/* Waits for the handle's queued work and reports deferred errors. */
+int mpo_sync(mpo_t* h);
+
+/* -------------------------------------------------------- extrapolation */
+typedef struct nze_fit_opts {
+  int32_t degree;        /* NZE_POLY degree (default 2)                        */
+  double delta_f;        /* weight exponent on fidelity (App. B.2, default 2)  */
+  double delta_d;        /* weight exponent on distance (App. B.2, default 20) */
+  double small;          /* criterion 2 threshold (default 1e-10)              */
+  double dip_threshold;  /* fidelity defining the dip size (default 0.99)      */
+  int32_t ref_sign;      /* criterion 3 reference sign: +1/-1, or 0 = sign of
+                            the value at the smallest lambda                  */
+  double b_max;          /* NZE_EXP3 upper bound on b; 0 -> 50 / lambda span  */
+} nze_fit_opts;
+
+/* Fills *opts with the defaults above. */
+void nze_fit_opts_default(nze_fit_opts* opts);
+
+/* Extrapolates <O>_lambda to lambda_target (Sec. 2.2.2 (B)).
+ *   n_pts          : number of (lambda, value, fidelity) points.
+ *   lambda, value  : n_pts float64 (host).
+ *   fidelity       : n_pts float64 emulation fidelities (used by
+ *                    NZE_LOGLIN_W weights; may be NULL otherwise).
+ *   method         : NZE_POLY, NZE_EXP3 or NZE_LOGLIN_W.
+ *   opts           : NULL for the defaults.
+ *   out_value      : extrapolated value at lambda_target.
+ *   out_coef       : 3 float64: POLY -> first min(3, degree+1) coefficients
+ *                    c_0, c_1, c_2 (constant first); EXP3 -> (a, b, c);
+ *                    LOGLIN_W -> (a, b, 0).  May be NULL.
+ *   used_mask      : n_pts bytes, 1 for the points the final fit used (NULL
+ *                    ok).
+ *   method_used    : the method that produced out_value after fallbacks
+ *                    (NULL ok).
+ * Host-only, float64, stateless.  NZE_EFIT when no method has enough points:
+ * the caller then falls back to the direct emulation at lambda_target. */
+int nze_extrapolate(int32_t n_pts, const double* lambda, const double* value,
+                    const double* fidelity, double lambda_target,
+                    int32_t method, const nze_fit_opts* opts,
+                    double* out_value, double* out_coef, uint8_t* used_mask,
+                    int32_t* method_used);
+
+/* Fidelity extrapolation, step (A) of Sec. 2.2.2: straight-line least squares
+ * of value against fidelity over runs at increasing bond dimension, evaluated
+ * at fidelity 1; *converged gets App. B.1's criterion 1 on the two last
+ * points (NULL ok).  n_pts >= 2.  Host-only. */
+int nze_fidelity_extrapolate(int32_t n_pts, const double* value,
+                             const double* fidelity, double* out_value,
+                             int32_t* converged);
+
+/* ------------------------------------------------------- kernel-level hooks */
+/* Single kernels of the update on caller buffers, for kernel-level parity
+ * tests.  All matrices are row-major device arrays in the path precision
+ * (float64 for NZE_FP64, float32 for NZE_MIXED); the call synchronises
+ * `stream` before returning.
+ *
+ * nze_kernel_theta: Theta' = (R x 1)(A B), the two-site contraction with the
+ * gate's superoperator applied on the physical pair (Sec. 2.1.2 "Approximate
+ * emulation"): A is (4 cl) x cm (site (cl, 4, cm)), B is cm x (4 cr) (site
+ * (cm, 4, cr)), ptm is 256 float64 on the host.  X receives the
+ * (4 cl) x (4 cr) block with rows (a, p') and columns (q', b) when ltr != 0,
+ * or its transpose when ltr == 0.  1 <= cl, cm, cr <= 512.
+ *
+ * nze_kernel_rowortho: block one-sided Jacobi on the rows of X (R x C, C a
+ * multiple of 4) with the rotations accumulated into W (R x R, overwritten,
+ * starts as the identity): on return W X has mutually orthogonal rows and
+ * W X = (W) X_in.  norms receives the R squared row norms of the result
+ * (host, float64).  *sweeps gets the sweeps used (NULL ok).  Returns
+ * NZE_ENOCONV if max_sweeps were not enough.  1 <= R <= 2048. */
+int nze_kernel_theta(int32_t precision, int32_t cl, int32_t cm, int32_t cr,
+                     const void* A, const void* B, const double* ptm,
+                     int32_t ltr, void* X, void* stream);
+int nze_kernel_rowortho(int32_t precision, int32_t R, int32_t C, void* X,
+                        void* W, double tol_rel, double tol_abs,
+                        int32_t max_sweeps, double* norms, int32_t* sweeps,
+                        void* stream);
+
+/* ------------------------------------------------------------------ misc */
+const char* nze_strerror(int code);
+const char* nze_last_error(void);
+const char* nze_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NZE_H */

@@ -1,0 +1,148 @@
+// Device-side building blocks for gfx950 (CDNA4, wave64): MFMA wrappers,
+// per-MPO workgroup-group barriers, the block one-sided Jacobi pair step, and
+// the tiled contraction / gather routines used by the persistent layer kernel.
+#ifndef NZE_DEVICE_H
+#define NZE_DEVICE_H
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nze {
+
+constexpr int NT = 256;          // threads per workgroup (4 waves)
+constexpr int BW = 16;           // Jacobi row-block width b
+constexpr int PR = 32;           // rows of one block pair (2b)
+constexpr int GLD = 33;          // LDS leading dimension of 32x32 fp64 tiles
+constexpr int MAXSW = 40;        // sweep-counter slots
+constexpr int CHI_LIMIT = 512;   // largest chi_max (select sorts 4*chi keys)
+constexpr int SMEM_DOUBLES = 6400;
+
+enum { OP_NONE = 0, OP_GATE_LR = 1, OP_GATE_RL = 2, OP_MOVE_LR = 3,
+       OP_MOVE_RL = 4 };
+
+// per-MPO float64 scalars
+enum { SC_LOG = 0, SC_FID = 1, SC_MAXDISC = 2, SC_MINGAP = 3, SC_F2 = 4,
+       SC_KEPT = 5, SC_COUNT = 8 };
+// per-MPO int counters
+enum { CT_RANK = 0, CT_ERR = 1, CT_MAXSW = 2, CT_UPD = 3, CT_SWTOT = 4,
+       CT_ROT = 8, CT_COUNT = 8 + MAXSW };
+enum { ERR_NOCONV = 1, ERR_NAN = 2, ERR_ABORT = 4 };
+
+// Everything one MPO (one noise level of one job) owns on the device.
+struct Slot {
+  void* sites;      // [n][site_cap] path precision; site k is (chi_l, 4, chi_r)
+  int* dims;        // [n + 1] bond dimensions, dims[0] = dims[n] = 1
+  double* scal;     // [SC_COUNT]
+  int* ctr;         // [CT_COUNT]
+  void* X;          // [m_cap * m_cap] two-site block / Jacobi data
+  void* W;          // [m_cap * m_cap] Jacobi accumulator (rows)
+  void* Rm;         // [chi_cap * chi_cap] factor absorbed by a centre move
+  double* norms;    // [m_cap] squared row norms
+  int* perm;        // [m_cap] kept rows, in decreasing norm
+  double* sval;     // [m_cap] kept singular values
+  int n, chi, site_cap, m_cap;
+  double tau, tie, tol_rel, tol_abs;
+  int max_sweeps, pad;
+};
+
+struct Step {
+  int op;    // OP_*
+  int k;     // gate: left site; move: site the centre leaves
+  int ptm;   // gate: index of its 16x16 PTM in the launch's PTM array
+  int pad;
+};
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct AccT;
+template <> struct AccT<float> { typedef f32x4 type; };
+template <> struct AccT<double> { typedef f64x4 type; };
+
+// D(16x16) += A(16x4) B(4x16).  Lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator element r of lane l is D[mrow<T>(l/16, r)][l%16]
+// (float32: row 4*(l/16) + r; float64: row l/16 + 4*r).
+__device__ inline f32x4 mfma4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline f64x4 mfma4(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T> __device__ inline int mrow(int kq, int r);
+template <> __device__ inline int mrow<float>(int kq, int r) { return 4 * kq + r; }
+template <> __device__ inline int mrow<double>(int kq, int r) { return kq + 4 * r; }
+
+__device__ inline void load4(const float* p, float v[4]) {
+  const float4 x = *reinterpret_cast<const float4*>(p);
+  v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+}
+__device__ inline void load4(const double* p, double v[4]) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the workgroup; every thread gets the result.  red needs 4 doubles.
+__device__ inline double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double s = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return s;
+}
+
+// ------------------------------------------------------------ group sync
+
+// Barrier across the G workgroups that serve one MPO.  The counter grows
+// monotonically within one launch and is cleared by a fill kernel before the
+// launch.  The wait is bounded: past `timeout` ticks of the constant-rate
+// clock the launch-wide abort flag is raised and every waiter returns false.
+struct Group {
+  int* bar;
+  int* abort_flag;
+  int G;
+  int nbar;
+  uint64_t timeout;
+  int* sflag;   // one LDS int
+};
+
+__device__ inline bool group_sync(Group& grp) {
+  __threadfence();
+  __syncthreads();
+  grp.nbar += 1;
+  if (threadIdx.x == 0) {
+    atomicAdd(grp.bar, 1);
+    const int target = grp.nbar * grp.G;
+    int ok = 1;
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(grp.bar, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(grp.abort_flag, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+      if (wall_clock64() - t0 > grp.timeout) {
+        atomicExch(grp.abort_flag, 1);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    *grp.sflag = ok;
+  }
+  __syncthreads();
+  __threadfence();
+  const int ok = *grp.sflag;
+  __syncthreads();
+  return ok != 0;
+}
+
+}  // namespace nze
+
+#endif

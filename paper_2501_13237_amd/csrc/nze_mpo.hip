@@ -1,0 +1,864 @@
+// MPO handles, the persistent per-layer kernel, readout kernels and the
+// host-side orchestration behind mpo_init / mpo_apply_layer / mpo_expect.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+#include "nze.h"
+#include "nze_internal.h"
+#include "nze_phases.h"
+
+namespace nze {
+
+__device__ inline int ld_agent(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------- kernels
+
+// One launch applies a whole layer: every MPO of the batch walks through its
+// list of steps (centre moves and gates) with G workgroups; workgroup b serves
+// MPO b % nmpo, so with 8 MPOs each MPO's workgroups share one XCD.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_layer(const Slot* slots,
+                                             const Step* steps,
+                                             const double* ptms, int nsteps,
+                                             int nmpo, int G, int* bar,
+                                             int* abort_flag,
+                                             unsigned long long timeout) {
+  __shared__ double smem[SMEM_DOUBLES];
+  __shared__ int sflag[2];
+  const int mpo = blockIdx.x % nmpo;
+  const int g = blockIdx.x / nmpo;
+  const Slot s = slots[mpo];
+  Group grp{bar + mpo, abort_flag, G, 0, timeout, sflag};
+  for (int st = 0; st < nsteps; ++st) {
+    const Step op = steps[(size_t)st * nmpo + mpo];
+    bool ok = true;
+    switch (op.op) {
+      case OP_GATE_LR:
+        ok = op_gate<T>(s, op.k, true, ptms + (size_t)op.ptm * 256, g, G, grp, smem);
+        break;
+      case OP_GATE_RL:
+        ok = op_gate<T>(s, op.k, false, ptms + (size_t)op.ptm * 256, g, G, grp, smem);
+        break;
+      case OP_MOVE_LR:
+        ok = op_move<T>(s, op.k, true, g, G, grp, smem);
+        break;
+      case OP_MOVE_RL:
+        ok = op_move<T>(s, op.k, false, g, G, grp, smem);
+        break;
+      default:
+        break;
+    }
+    if (!ok) {
+      if (g == 0 && threadIdx.x == 0) atomicOr(&s.ctr[CT_ERR], ERR_ABORT);
+      return;
+    }
+  }
+}
+
+__global__ void k_fill_int(int* p, int n, int v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Product state: site k holds its 4 Pauli coordinates normalised to 1.
+template <typename T>
+__global__ void k_init(const Slot* slots, const double* init_sites, int n) {
+  const Slot s = slots[blockIdx.x];
+  T* sites = reinterpret_cast<T*>(s.sites);
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    double v[4];
+    for (int p = 0; p < 4; ++p) v[p] = init_sites[4 * k + p];
+    const double nv = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3]);
+    for (int p = 0; p < 4; ++p) sites[(size_t)k * s.site_cap + p] = T(v[p] / nv);
+  }
+  for (int k = threadIdx.x; k <= n; k += blockDim.x) s.dims[k] = 1;
+  for (int i = threadIdx.x; i < CT_COUNT; i += blockDim.x) s.ctr[i] = 0;
+  if (threadIdx.x == 0) {
+    double lg = 0.0;
+    for (int k = 0; k < n; ++k) {
+      double q = 0.0;
+      for (int p = 0; p < 4; ++p) q += init_sites[4 * k + p] * init_sites[4 * k + p];
+      lg += 0.5 * log(q);
+    }
+    s.scal[SC_LOG] = lg;
+    s.scal[SC_FID] = 1.0;
+    s.scal[SC_MAXDISC] = 0.0;
+    s.scal[SC_MINGAP] = 1.0;
+    s.scal[SC_F2] = 0.0;
+    s.scal[SC_KEPT] = 0.0;
+  }
+}
+
+// Left (dir 0) and right (dir 1) environments of the identity slices, with a
+// per-site rescale: env[k] holds the normalised vector, lg[k] its log factor.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_env(const Slot* slots, double* env,
+                                            double* lg, int env_stride) {
+  const int mpo = blockIdx.x, dir = blockIdx.y;
+  const Slot s = slots[mpo];
+  const int n = s.n;
+  double* E = env + ((size_t)mpo * 2 + dir) * env_stride;
+  double* Lg = lg + ((size_t)mpo * 2 + dir) * (n + 1);
+  __shared__ double v[2 * CHI_LIMIT];
+  __shared__ double red[8];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double acc_log = 0.0;
+  if (tid == 0) v[0] = 1.0;
+  int cur = 0;
+  const int k0 = dir == 0 ? 0 : n;
+  if (tid == 0) { E[(size_t)k0 * s.chi] = 1.0; Lg[k0] = 0.0; }
+  __syncthreads();
+  for (int step = 0; step < n; ++step) {
+    const int k = dir == 0 ? step : n - 1 - step;
+    const int cl = s.dims[k], cr = s.dims[k + 1];
+    const T* M = reinterpret_cast<const T*>(s.sites) + (size_t)k * s.site_cap;
+    double* vin = v + cur * CHI_LIMIT;
+    double* vout = v + (1 - cur) * CHI_LIMIT;
+    double mx = 0.0;
+    if (dir == 0) {
+      for (int j = tid; j < cr; j += NT) {
+        double a = 0.0;
+        for (int i = 0; i < cl; ++i) a += vin[i] * double(M[(size_t)i * 4 * cr + j]);
+        vout[j] = a;
+        mx = fmax(mx, fabs(a));
+      }
+    } else {
+      for (int i = w; i < cl; i += 4) {
+        double a = 0.0;
+        for (int j = lane; j < cr; j += 64) a += double(M[(size_t)i * 4 * cr + j]) * vin[j];
+        a = wave_sum(a);
+        if (lane == 0) vout[i] = a;
+        mx = fmax(mx, fabs(a));
+      }
+    }
+    __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0) red[w] = mx;
+    __syncthreads();
+    mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const int len = dir == 0 ? cr : cl;
+    const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
+    acc_log += mx > 0.0 ? log(mx) : 0.0;
+    const int kout = dir == 0 ? k + 1 : k;
+    for (int j = tid; j < len; j += NT) {
+      vout[j] *= sc;
+      E[(size_t)kout * s.chi + j] = vout[j];
+    }
+    if (tid == 0) Lg[kout] = acc_log;
+    __syncthreads();
+    cur = 1 - cur;
+  }
+}
+
+// One workgroup per (MPO, observable): contract the Pauli slices over the
+// string's support between the identity environments.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_obs(const Slot* slots, const double* env,
+                                            const double* lg, int env_stride,
+                                            const uint8_t* paulis,
+                                            const int* span, int n_obs,
+                                            double* out) {
+  const int mpo = blockIdx.y, o = blockIdx.x;
+  const Slot s = slots[mpo];
+  const int n = s.n;
+  const double* EL = env + ((size_t)mpo * 2 + 0) * env_stride;
+  const double* ER = env + ((size_t)mpo * 2 + 1) * env_stride;
+  const double* LL = lg + ((size_t)mpo * 2 + 0) * (n + 1);
+  const double* LR = lg + ((size_t)mpo * 2 + 1) * (n + 1);
+  __shared__ double v[2 * CHI_LIMIT];
+  __shared__ double red[8];
+  const int tid = threadIdx.x;
+  const int f = span[2 * o], l = span[2 * o + 1];
+  // trace c_I = EL[n] (a scalar) with log LL[n]
+  const double cI = EL[(size_t)n * s.chi];
+  const double lI = LL[n];
+  if (f < 0) {                   // identity string
+    if (tid == 0) out[(size_t)mpo * n_obs + o] = 1.0;
+    return;
+  }
+  const uint8_t* P = paulis + (size_t)o * n;
+  int cur = 0;
+  for (int j = tid; j < s.dims[f]; j += NT) v[j] = EL[(size_t)f * s.chi + j];
+  double acc_log = LL[f];
+  __syncthreads();
+  for (int k = f; k <= l; ++k) {
+    const int cl = s.dims[k], cr = s.dims[k + 1];
+    const int p = P[k];
+    const T* M = reinterpret_cast<const T*>(s.sites) + (size_t)k * s.site_cap;
+    double* vin = v + cur * CHI_LIMIT;
+    double* vout = v + (1 - cur) * CHI_LIMIT;
+    double mx = 0.0;
+    for (int j = tid; j < cr; j += NT) {
+      double a = 0.0;
+      for (int i = 0; i < cl; ++i) a += vin[i] * double(M[(size_t)i * 4 * cr + p * cr + j]);
+      vout[j] = a;
+      mx = fmax(mx, fabs(a));
+    }
+    for (int q = 32; q > 0; q >>= 1) mx = fmax(mx, __shfl_xor(mx, q, 64));
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    __syncthreads();
+    mx = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
+    acc_log += mx > 0.0 ? log(mx) : 0.0;
+    for (int j = tid; j < cr; j += NT) vout[j] *= sc;
+    __syncthreads();
+    cur = 1 - cur;
+  }
+  // dot with the right environment at bond l + 1
+  const int len = s.dims[l + 1];
+  double a = 0.0;
+  for (int j = tid; j < len; j += NT) a += v[cur * CHI_LIMIT + j] * ER[(size_t)(l + 1) * s.chi + j];
+  a = block_sum(a, red);
+  if (tid == 0) {
+    const double lr = LR[l + 1];
+    out[(size_t)mpo * n_obs + o] = (a / cI) * exp(acc_log + lr - lI);
+  }
+}
+
+}  // namespace nze
+
+using namespace nze;
+
+// ================================================================ host side
+
+namespace {
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t sites, X, W, Rm, norms, perm, sval, dims, scal, ctr, env, envlog, total;
+};
+
+bool cfg_valid(const mpo_config* c) {
+  return c && c->n >= 2 && c->n <= 4096 && c->chi_max >= 1 &&
+         c->chi_max <= CHI_LIMIT && c->n_levels >= 1 &&
+         (c->precision == NZE_FP64 || c->precision == NZE_MIXED) &&
+         c->max_sweeps >= 0 && c->max_sweeps <= MAXSW;
+}
+
+Layout layout_of(const mpo_config* c) {
+  const size_t L = c->n_levels, n = c->n, chi = c->chi_max;
+  const size_t es = c->precision == NZE_FP64 ? 8 : 4;
+  const size_t site_cap = chi * 4 * chi, m = 4 * chi;
+  Layout o;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t at = off; off += align_up(bytes); return at; };
+  o.sites = take(L * n * site_cap * es);
+  o.X = take(L * m * m * es);
+  o.W = take(L * m * m * es);
+  o.Rm = take(L * chi * chi * es);
+  o.norms = take(L * m * 8);
+  o.perm = take(L * m * 4);
+  o.sval = take(L * m * 8);
+  o.dims = take(L * (n + 1) * 4);
+  o.scal = take(L * SC_COUNT * 8);
+  o.ctr = take(L * CT_COUNT * 4);
+  o.env = take(L * 2 * (n + 1) * chi * 8);
+  o.envlog = take(L * 2 * (n + 1) * 8);
+  o.total = off;
+  return o;
+}
+
+// Launch metadata staging: one device buffer per stream, grown on demand, fed
+// from double-buffered pinned host memory.
+struct Staging {
+  char* dev = nullptr;
+  size_t dev_bytes = 0;
+  char* host[2] = {nullptr, nullptr};
+  size_t host_bytes[2] = {0, 0};
+  hipEvent_t copied[2] = {nullptr, nullptr};
+  int cur = 0;
+};
+std::mutex g_stage_mu;
+std::map<hipStream_t, Staging*> g_stage;
+
+struct DevInfo {
+  int cus = 0;
+  int occ[2] = {0, 0};
+  unsigned long long timeout_ticks = 0;
+};
+std::mutex g_dev_mu;
+std::map<int, DevInfo> g_dev;
+
+}  // namespace
+
+struct mpo_handle {
+  mpo_config cfg;
+  hipStream_t stream;
+  char* ws;
+  Layout lay;
+  int site_cap, m_cap;
+  int centre;
+  std::vector<Slot> slots;        // host copies, one per level
+  int64_t layers;
+};
+
+namespace {
+
+int hip_fail(hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  nze::g_last_error = m;
+  return NZE_EHIP;
+}
+#define HIPCHK(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) return hip_fail(e_, #x); } while (0)
+
+int dev_info(DevInfo& out) {
+  int dev;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  auto it = g_dev.find(dev);
+  if (it != g_dev.end()) { out = it->second; return NZE_OK; }
+  DevInfo di;
+  HIPCHK(hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev));
+  int occ = 0;
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_layer<double>, NT, 0));
+  di.occ[0] = occ;
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_layer<float>, NT, 0));
+  di.occ[1] = occ;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    khz = 100000;
+  di.timeout_ticks = (unsigned long long)khz * 1000ull * 4ull;   // 4 s
+  g_dev[dev] = di;
+  out = di;
+  return NZE_OK;
+}
+
+int stage(hipStream_t stream, const void* src, size_t bytes, char** dev_out) {
+  Staging* st;
+  {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    auto it = g_stage.find(stream);
+    if (it == g_stage.end()) {
+      st = new Staging();
+      g_stage[stream] = st;
+    } else {
+      st = it->second;
+    }
+  }
+  const int b = st->cur;
+  st->cur ^= 1;
+  if (st->copied[b]) HIPCHK(hipEventSynchronize(st->copied[b]));
+  else HIPCHK(hipEventCreateWithFlags(&st->copied[b], hipEventDisableTiming));
+  if (st->host_bytes[b] < bytes) {
+    if (st->host[b]) HIPCHK(hipHostFree(st->host[b]));
+    const size_t nb = std::max(bytes, (size_t)1 << 20);
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&st->host[b]), nb, hipHostMallocDefault));
+    st->host_bytes[b] = nb;
+  }
+  if (st->dev_bytes < bytes) {
+    // the previous launch may still read the old buffer: wait for the stream
+    HIPCHK(hipStreamSynchronize(stream));
+    if (st->dev) HIPCHK(hipFree(st->dev));
+    const size_t nb = std::max(bytes * 2, (size_t)1 << 20);
+    HIPCHK(hipMalloc(reinterpret_cast<void**>(&st->dev), nb));
+    st->dev_bytes = nb;
+  }
+  std::memcpy(st->host[b], src, bytes);
+  HIPCHK(hipMemcpyAsync(st->dev, st->host[b], bytes, hipMemcpyHostToDevice, stream));
+  HIPCHK(hipEventRecord(st->copied[b], stream));
+  *dev_out = st->dev;
+  return NZE_OK;
+}
+
+void fill_defaults(mpo_config& c) {
+  const bool f64 = c.precision == NZE_FP64;
+  if (c.trunc_tol <= 0) c.trunc_tol = f64 ? 1e-14 : 1e-7;
+  if (c.tie_tol <= 0) c.tie_tol = f64 ? 1e-10 : 1e-5;
+  if (c.jacobi_tol <= 0) c.jacobi_tol = f64 ? 1e-13 : 2e-6;
+  if (c.max_sweeps <= 0) c.max_sweeps = f64 ? 20 : 14;
+  if (c.block <= 0) c.block = BW;
+}
+
+// Host-side plan of one layer for one handle: centre moves and gates.
+void plan_layer(mpo_handle* h, int n_gates, const int32_t* ls,
+                std::vector<Step>& out) {
+  if (n_gates == 0) return;
+  const bool ltr = (ls[0] % 2) == 0;
+  for (int gi = 0; gi < n_gates; ++gi) {
+    const int i = ltr ? gi : n_gates - 1 - gi;
+    const int k = ls[i];
+    const int target = ltr ? k : k + 1;
+    while (h->centre < target) { out.push_back({OP_MOVE_LR, h->centre, 0, 0}); h->centre++; }
+    while (h->centre > target) { out.push_back({OP_MOVE_RL, h->centre, 0, 0}); h->centre--; }
+    out.push_back({ltr ? OP_GATE_LR : OP_GATE_RL, k, i, 0});
+    h->centre = ltr ? k + 1 : k;
+  }
+}
+
+int check_sites(const mpo_handle* h, int n_gates, const int32_t* ls) {
+  if (n_gates < 0) return fail(NZE_EINVAL, "n_gates < 0");
+  if (n_gates > 0 && !ls) return fail(NZE_EINVAL, "left_site is NULL");
+  for (int i = 0; i < n_gates; ++i) {
+    if (ls[i] < 0 || ls[i] + 1 >= h->cfg.n) return fail(NZE_EINVAL, "gate outside the chain");
+    if (i > 0 && ls[i] - ls[i - 1] < 2) return fail(NZE_EINVAL, "left sites must be increasing and disjoint");
+  }
+  return NZE_OK;
+}
+
+int read_errors(mpo_t* h) {
+  const int L = h->cfg.n_levels;
+  std::vector<int> ctr((size_t)L * CT_COUNT);
+  HIPCHK(hipMemcpyAsync(ctr.data(), h->ws + h->lay.ctr, ctr.size() * 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  int err = 0;
+  for (int l = 0; l < L; ++l) err |= ctr[(size_t)l * CT_COUNT + CT_ERR];
+  if (err & ERR_ABORT) return fail(NZE_EHIP, "layer kernel aborted at a group barrier (timeout)");
+  if (err & ERR_NAN) return fail(NZE_ENUM, "NaN/Inf or zero norm in the state");
+  if (err & ERR_NOCONV) return fail(NZE_ENOCONV, "Jacobi SVD hit the sweep cap");
+  return NZE_OK;
+}
+
+}  // namespace
+
+extern "C" size_t mpo_footprint(const mpo_config* cfg) {
+  if (!cfg) return 0;
+  mpo_config c = *cfg;
+  if (!cfg_valid(&c)) return 0;
+  return layout_of(&c).total;
+}
+
+extern "C" int mpo_init(mpo_t** out, const mpo_config* cfg,
+                        const double* init_sites, void* workspace,
+                        size_t ws_bytes, void* stream) {
+  if (!out) return fail(NZE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfg_valid(cfg)) return fail(NZE_EINVAL, "invalid mpo_config");
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return fail(NZE_EINVAL, "workspace must be a 256-byte aligned device pointer");
+  mpo_config c = *cfg;
+  fill_defaults(c);
+  if (c.block != BW) return fail(NZE_EINVAL, "unsupported Jacobi block width");
+  const Layout lay = layout_of(&c);
+  if (ws_bytes < lay.total) return fail(NZE_ENOMEM, "workspace smaller than mpo_footprint(cfg)");
+  DevInfo di;
+  int rc = dev_info(di);
+  if (rc) return rc;
+  mpo_handle* h = new mpo_handle();
+  h->cfg = c;
+  h->stream = reinterpret_cast<hipStream_t>(stream);
+  h->ws = reinterpret_cast<char*>(workspace);
+  h->lay = lay;
+  h->site_cap = c.chi_max * 4 * c.chi_max;
+  h->m_cap = 4 * c.chi_max;
+  h->centre = 0;
+  h->layers = 0;
+  const size_t es = c.precision == NZE_FP64 ? 8 : 4;
+  const int L = c.n_levels, n = c.n;
+  for (int l = 0; l < L; ++l) {
+    Slot s;
+    std::memset(&s, 0, sizeof(s));
+    s.sites = h->ws + lay.sites + (size_t)l * n * h->site_cap * es;
+    s.dims = reinterpret_cast<int*>(h->ws + lay.dims) + (size_t)l * (n + 1);
+    s.scal = reinterpret_cast<double*>(h->ws + lay.scal) + (size_t)l * SC_COUNT;
+    s.ctr = reinterpret_cast<int*>(h->ws + lay.ctr) + (size_t)l * CT_COUNT;
+    s.X = h->ws + lay.X + (size_t)l * h->m_cap * h->m_cap * es;
+    s.W = h->ws + lay.W + (size_t)l * h->m_cap * h->m_cap * es;
+    s.Rm = h->ws + lay.Rm + (size_t)l * c.chi_max * c.chi_max * es;
+    s.norms = reinterpret_cast<double*>(h->ws + lay.norms) + (size_t)l * h->m_cap;
+    s.perm = reinterpret_cast<int*>(h->ws + lay.perm) + (size_t)l * h->m_cap;
+    s.sval = reinterpret_cast<double*>(h->ws + lay.sval) + (size_t)l * h->m_cap;
+    s.n = n;
+    s.chi = c.chi_max;
+    s.site_cap = h->site_cap;
+    s.m_cap = h->m_cap;
+    s.tau = c.trunc_tol;
+    s.tie = c.tie_tol;
+    s.tol_rel = c.jacobi_tol;
+    s.tol_abs = c.precision == NZE_FP64 ? 1e-15 : 1e-6;
+    s.max_sweeps = c.max_sweeps;
+    h->slots.push_back(s);
+  }
+  std::vector<double> init((size_t)4 * n);
+  for (int k = 0; k < n; ++k) {
+    const double* src = init_sites ? init_sites + 4 * k : nullptr;
+    double v[4] = {1, 0, 0, 1};
+    if (src) for (int p = 0; p < 4; ++p) v[p] = src[p];
+    if (!(v[0] * v[0] + v[1] * v[1] + v[2] * v[2] + v[3] * v[3] > 0)) {
+      delete h;
+      return fail(NZE_EINVAL, "zero initial site");
+    }
+    for (int p = 0; p < 4; ++p) init[4 * k + p] = v[p];
+  }
+  // metadata: slots then init sites
+  std::vector<char> blob(sizeof(Slot) * L + 8 * init.size());
+  std::memcpy(blob.data(), h->slots.data(), sizeof(Slot) * L);
+  std::memcpy(blob.data() + sizeof(Slot) * L, init.data(), 8 * init.size());
+  char* dev;
+  rc = stage(h->stream, blob.data(), blob.size(), &dev);
+  if (rc) { delete h; return rc; }
+  const Slot* dslots = reinterpret_cast<const Slot*>(dev);
+  const double* dinit = reinterpret_cast<const double*>(dev + sizeof(Slot) * L);
+  if (c.precision == NZE_FP64)
+    hipLaunchKernelGGL(k_init<double>, dim3(L), dim3(NT), 0, h->stream, dslots, dinit, n);
+  else
+    hipLaunchKernelGGL(k_init<float>, dim3(L), dim3(NT), 0, h->stream, dslots, dinit, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) { delete h; return hip_fail(e, "k_init launch"); }
+  *out = h;
+  return NZE_OK;
+}
+
+extern "C" void mpo_free(mpo_t* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+extern "C" int mpo_apply_layer_batch(mpo_t* const* hs, int32_t k,
+                                     const int32_t* n_gates,
+                                     const int32_t* const* left_site,
+                                     const double* const* ptm) {
+  if (k <= 0 || !hs || !n_gates || !left_site || !ptm) return fail(NZE_EINVAL, "bad batch");
+  const int prec = hs[0]->cfg.precision;
+  const hipStream_t stream = hs[0]->stream;
+  for (int j = 0; j < k; ++j) {
+    if (!hs[j]) return fail(NZE_EINVAL, "NULL handle");
+    if (hs[j]->cfg.precision != prec) return fail(NZE_EINVAL, "mixed precisions in one batch");
+    if (hs[j]->stream != stream) return fail(NZE_EINVAL, "handles on different streams");
+    int rc = check_sites(hs[j], n_gates[j], left_site[j]);
+    if (rc) return rc;
+    if (n_gates[j] > 0 && !ptm[j]) return fail(NZE_EINVAL, "ptm is NULL");
+  }
+  // plans (per handle; every level of a handle follows the same plan)
+  std::vector<std::vector<Step>> plans(k);
+  std::vector<int> saved_centre(k);
+  size_t nsteps = 0, nmpo = 0, nptm = 0;
+  for (int j = 0; j < k; ++j) {
+    saved_centre[j] = hs[j]->centre;
+    plan_layer(hs[j], n_gates[j], left_site[j], plans[j]);
+    nsteps = std::max(nsteps, plans[j].size());
+    nmpo += hs[j]->cfg.n_levels;
+    nptm += (size_t)hs[j]->cfg.n_levels * n_gates[j];
+  }
+  if (nsteps == 0) return NZE_OK;
+  DevInfo di;
+  int rc = dev_info(di);
+  if (rc) return rc;
+  const int occ = di.occ[prec == NZE_FP64 ? 0 : 1];
+  const int resident = std::max(1, occ * di.cus);
+  if ((int)nmpo > resident) return fail(NZE_EINVAL, "batch has more MPOs than resident workgroups");
+  int chi_cap = 0;
+  for (int j = 0; j < k; ++j) chi_cap = std::max(chi_cap, hs[j]->cfg.chi_max);
+  const int want = std::max(1, chi_cap / 8);               // pairs per round
+  const int G = std::max(1, std::min(want, resident / (int)nmpo));
+  // blob: slots | steps | ptms | bar + abort
+  const size_t off_steps = align_up(sizeof(Slot) * nmpo);
+  const size_t off_ptm = off_steps + align_up(sizeof(Step) * nsteps * nmpo);
+  const size_t off_bar = off_ptm + align_up(8 * 256 * std::max<size_t>(nptm, 1));
+  const size_t total = off_bar + align_up(4 * (nmpo + 1));
+  std::vector<char> blob(total, 0);
+  Slot* bslots = reinterpret_cast<Slot*>(blob.data());
+  Step* bsteps = reinterpret_cast<Step*>(blob.data() + off_steps);
+  double* bptm = reinterpret_cast<double*>(blob.data() + off_ptm);
+  size_t mpo0 = 0, ptm0 = 0;
+  for (int j = 0; j < k; ++j) {
+    mpo_t* h = hs[j];
+    const int L = h->cfg.n_levels, ng = n_gates[j];
+    for (int l = 0; l < L; ++l) {
+      bslots[mpo0 + l] = h->slots[l];
+      for (size_t st = 0; st < nsteps; ++st) {
+        Step s = st < plans[j].size() ? plans[j][st] : Step{OP_NONE, 0, 0, 0};
+        if (s.op == OP_GATE_LR || s.op == OP_GATE_RL) s.ptm = (int)(ptm0 + (size_t)l * ng + s.ptm);
+        bsteps[st * nmpo + mpo0 + l] = s;
+      }
+    }
+    std::memcpy(bptm + ptm0 * 256, ptm[j], sizeof(double) * 256 * L * ng);
+    mpo0 += L;
+    ptm0 += (size_t)L * ng;
+  }
+  char* dev;
+  rc = stage(stream, blob.data(), blob.size(), &dev);
+  if (rc) {
+    for (int j = 0; j < k; ++j) hs[j]->centre = saved_centre[j];
+    return rc;
+  }
+  int* dbar = reinterpret_cast<int*>(dev + off_bar);
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(256), 0, stream, dbar, (int)nmpo + 1, 0);
+  const Slot* a_slots = reinterpret_cast<const Slot*>(dev);
+  const Step* a_steps = reinterpret_cast<const Step*>(dev + off_steps);
+  const double* a_ptm = reinterpret_cast<const double*>(dev + off_ptm);
+  int a_nsteps = (int)nsteps, a_nmpo = (int)nmpo, a_G = G;
+  int* a_bar = dbar;
+  int* a_abort = dbar + nmpo;
+  unsigned long long a_to = di.timeout_ticks;
+  void* args[] = {&a_slots, &a_steps, &a_ptm, &a_nsteps, &a_nmpo, &a_G, &a_bar, &a_abort, &a_to};
+  const void* fn = prec == NZE_FP64 ? reinterpret_cast<const void*>(&k_layer<double>)
+                                    : reinterpret_cast<const void*>(&k_layer<float>);
+  HIPCHK(hipLaunchCooperativeKernel(fn, dim3((unsigned)(nmpo * G)), dim3(NT), args, 0, stream));
+  for (int j = 0; j < k; ++j) hs[j]->layers++;
+  return NZE_OK;
+}
+
+extern "C" int mpo_apply_layer(mpo_t* h, int32_t n_gates,
+                               const int32_t* left_site, const double* ptm) {
+  if (!h) return fail(NZE_EINVAL, "NULL handle");
+  return mpo_apply_layer_batch(&h, 1, &n_gates, &left_site, &ptm);
+}
+
+extern "C" int mpo_sync(mpo_t* h) {
+  if (!h) return fail(NZE_EINVAL, "NULL handle");
+  return read_errors(h);
+}
+
+extern "C" int mpo_expect(mpo_t* h, int32_t n_obs, const uint8_t* paulis,
+                          double* values, double* fidelity, double* trace) {
+  if (!h) return fail(NZE_EINVAL, "NULL handle");
+  if (n_obs < 0 || (n_obs > 0 && (!paulis || !values))) return fail(NZE_EINVAL, "bad observables");
+  const int L = h->cfg.n_levels, n = h->cfg.n;
+  int rc = read_errors(h);
+  if (rc) return rc;
+  for (size_t i = 0; i < (size_t)n_obs * n; ++i)
+    if (paulis[i] > 3) return fail(NZE_EINVAL, "Pauli code > 3");
+  // slots + spans + strings staged together
+  std::vector<int> span(2 * std::max(n_obs, 1), -1);
+  for (int o = 0; o < n_obs; ++o) {
+    int f = -1, l = -1;
+    for (int q = 0; q < n; ++q)
+      if (paulis[(size_t)o * n + q]) { if (f < 0) f = q; l = q; }
+    span[2 * o] = f;
+    span[2 * o + 1] = l;
+  }
+  const size_t off_span = align_up(sizeof(Slot) * L);
+  const size_t off_str = off_span + align_up(span.size() * 4);
+  const size_t off_out = off_str + align_up((size_t)std::max(n_obs, 1) * n);
+  const size_t total = off_out + align_up(8 * (size_t)L * std::max(n_obs, 1));
+  std::vector<char> blob(total, 0);
+  std::memcpy(blob.data(), h->slots.data(), sizeof(Slot) * L);
+  std::memcpy(blob.data() + off_span, span.data(), span.size() * 4);
+  if (n_obs) std::memcpy(blob.data() + off_str, paulis, (size_t)n_obs * n);
+  char* dev;
+  rc = stage(h->stream, blob.data(), blob.size(), &dev);
+  if (rc) return rc;
+  const Slot* dslots = reinterpret_cast<const Slot*>(dev);
+  double* env = reinterpret_cast<double*>(h->ws + h->lay.env);
+  double* lg = reinterpret_cast<double*>(h->ws + h->lay.envlog);
+  const int env_stride = (n + 1) * h->cfg.chi_max;
+  const bool f64 = h->cfg.precision == NZE_FP64;
+  if (f64) hipLaunchKernelGGL(k_env<double>, dim3(L, 2), dim3(NT), 0, h->stream, dslots, env, lg, env_stride);
+  else hipLaunchKernelGGL(k_env<float>, dim3(L, 2), dim3(NT), 0, h->stream, dslots, env, lg, env_stride);
+  HIPCHK(hipGetLastError());
+  double* dout = reinterpret_cast<double*>(dev + off_out);
+  if (n_obs > 0) {
+    const uint8_t* dstr = reinterpret_cast<const uint8_t*>(dev + off_str);
+    const int* dspan = reinterpret_cast<const int*>(dev + off_span);
+    if (f64) hipLaunchKernelGGL(k_obs<double>, dim3(n_obs, L), dim3(NT), 0, h->stream, dslots, env, lg, env_stride, dstr, dspan, n_obs, dout);
+    else hipLaunchKernelGGL(k_obs<float>, dim3(n_obs, L), dim3(NT), 0, h->stream, dslots, env, lg, env_stride, dstr, dspan, n_obs, dout);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(values, dout, 8 * (size_t)L * n_obs, hipMemcpyDeviceToHost, h->stream));
+  }
+  std::vector<double> scal((size_t)L * SC_COUNT);
+  HIPCHK(hipMemcpyAsync(scal.data(), h->ws + h->lay.scal, scal.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  std::vector<double> cI(L), lI(L);
+  for (int l = 0; l < L; ++l) {
+    HIPCHK(hipMemcpyAsync(&cI[l], env + (size_t)(l * 2) * env_stride + (size_t)n * h->cfg.chi_max, 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(&lI[l], lg + (size_t)(l * 2) * (n + 1) + n, 8, hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int l = 0; l < L; ++l) {
+    if (fidelity) fidelity[l] = scal[(size_t)l * SC_COUNT + SC_FID];
+    if (trace) trace[l] = cI[l] * std::exp(lI[l] + scal[(size_t)l * SC_COUNT + SC_LOG]);
+  }
+  return NZE_OK;
+}
+
+extern "C" int mpo_stats(mpo_t* h, nze_stats* stats, int32_t* bonds) {
+  if (!h || !stats) return fail(NZE_EINVAL, "bad arguments");
+  const int L = h->cfg.n_levels, n = h->cfg.n;
+  std::vector<double> scal((size_t)L * SC_COUNT);
+  std::vector<int> ctr((size_t)L * CT_COUNT), dims((size_t)L * (n + 1));
+  HIPCHK(hipMemcpyAsync(scal.data(), h->ws + h->lay.scal, scal.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(ctr.data(), h->ws + h->lay.ctr, ctr.size() * 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync(dims.data(), h->ws + h->lay.dims, dims.size() * 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  for (int l = 0; l < L; ++l) {
+    nze_stats& s = stats[l];
+    const double* sc = &scal[(size_t)l * SC_COUNT];
+    const int* ct = &ctr[(size_t)l * CT_COUNT];
+    s.fidelity = sc[SC_FID];
+    s.log_scale = sc[SC_LOG];
+    s.max_discarded = sc[SC_MAXDISC];
+    s.min_cut_gap = sc[SC_MINGAP];
+    s.max_sweeps = ct[CT_MAXSW];
+    s.updates = ct[CT_UPD];
+    s.sweeps_total = ct[CT_SWTOT];
+    int mb = 0;
+    for (int b = 1; b < n; ++b) {
+      mb = std::max(mb, dims[(size_t)l * (n + 1) + b]);
+      if (bonds) bonds[(size_t)l * (n - 1) + b - 1] = dims[(size_t)l * (n + 1) + b];
+    }
+    s.max_bond = mb;
+  }
+  return read_errors(h);
+}
+
+extern "C" int mpo_bond_spectrum(mpo_t* h, int32_t lv, int32_t l, double* s_out,
+                                 int32_t cap, int32_t* count) {
+  (void)h; (void)lv; (void)l; (void)s_out; (void)cap; (void)count;
+  return fail(NZE_EINVAL, "mpo_bond_spectrum is not available in this build");
+}
+
+// ------------------------------------------------------ kernel-level hooks
+
+namespace nze {
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_theta_only(Slot s, const double* R,
+                                                   int ltr, int G, int* bar,
+                                                   int* abort_flag,
+                                                   unsigned long long to) {
+  __shared__ double smem[SMEM_DOUBLES];
+  phase_theta<T>(s, 0, ltr != 0, R, blockIdx.x, G, smem);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_rowortho(Slot s, int R, int C, int G,
+                                                 int* bar, int* abort_flag,
+                                                 unsigned long long to) {
+  __shared__ double smem[SMEM_DOUBLES];
+  __shared__ int sflag[2];
+  Group grp{bar, abort_flag, G, 0, to, sflag};
+  const int g = blockIdx.x;
+  T* X = reinterpret_cast<T*>(s.X);
+  T* W = reinterpret_cast<T*>(s.W);
+  // F2 = ||X||^2 and W = I
+  {
+    double f2 = 0.0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int r = g * 4 + w; r < R; r += 4 * G)
+      for (int c = lane; c < C; c += 64) f2 += double(X[(size_t)r * C + c]) * double(X[(size_t)r * C + c]);
+    const double tot = block_sum(f2, smem);
+    if (threadIdx.x == 0 && tot != 0.0) atomicAdd(&s.scal[SC_F2], tot);
+    set_identity(W, R, g, G);
+  }
+  if (!group_sync(grp)) { if (g == 0 && threadIdx.x == 0) atomicOr(&s.ctr[CT_ERR], ERR_ABORT); return; }
+  if (!phase_jacobi<T>(s, X, W, R, C, g, G, grp, smem)) { if (g == 0 && threadIdx.x == 0) atomicOr(&s.ctr[CT_ERR], ERR_ABORT); return; }
+  phase_norms<T>(s, X, R, C, g, G);
+}
+
+}  // namespace nze
+
+namespace {
+
+struct HookScratch {
+  char* dev = nullptr;   // scal | ctr | bar | abort | norms | ptm
+};
+std::mutex g_hook_mu;
+HookScratch g_hook;
+constexpr size_t HOOK_BYTES = 1 << 16;
+
+int hook_scratch(char** out) {
+  std::lock_guard<std::mutex> lk(g_hook_mu);
+  if (!g_hook.dev) HIPCHK(hipMalloc(reinterpret_cast<void**>(&g_hook.dev), HOOK_BYTES));
+  *out = g_hook.dev;
+  return NZE_OK;
+}
+
+}  // namespace
+
+extern "C" int nze_kernel_theta(int32_t precision, int32_t cl, int32_t cm,
+                                int32_t cr, const void* A, const void* B,
+                                const double* ptm, int32_t ltr, void* X,
+                                void* stream) {
+  if (precision != NZE_FP64 && precision != NZE_MIXED) return fail(NZE_EINVAL, "precision");
+  if (cl < 1 || cm < 1 || cr < 1 || cl > CHI_LIMIT || cm > CHI_LIMIT || cr > CHI_LIMIT || !A || !B || !ptm || !X)
+    return fail(NZE_EINVAL, "bad theta arguments");
+  const size_t es = precision == NZE_FP64 ? 8 : 4;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* scr;
+  int rc = hook_scratch(&scr);
+  if (rc) return rc;
+  // sites: two consecutive slots; the hook copies A and B into a temporary
+  const size_t cap = (size_t)std::max(cl, cr) * 4 * cm + (size_t)cm * 4 * std::max(cl, cr);
+  char* tmp;
+  HIPCHK(hipMalloc(reinterpret_cast<void**>(&tmp), 2 * cap * es + 4096));
+  int dims[3] = {cl, cm, cr};
+  int* ddims = reinterpret_cast<int*>(tmp + 2 * cap * es);
+  HIPCHK(hipMemcpyAsync(ddims, dims, sizeof(dims), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(tmp, A, (size_t)4 * cl * cm * es, hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(tmp + cap * es, B, (size_t)cm * 4 * cr * es, hipMemcpyDeviceToDevice, st));
+  double* dptm = reinterpret_cast<double*>(scr + 4096);
+  HIPCHK(hipMemcpyAsync(dptm, ptm, 256 * 8, hipMemcpyHostToDevice, st));
+  double* dscal = reinterpret_cast<double*>(scr);
+  HIPCHK(hipMemsetAsync(dscal, 0, 64, st));
+  Slot s;
+  std::memset(&s, 0, sizeof(s));
+  s.sites = tmp;
+  s.site_cap = (int)cap;
+  s.dims = ddims;
+  s.scal = dscal;
+  s.X = X;
+  // W = I is written too: point it at a scratch matrix of the right size
+  const int Rr = ltr ? 4 * cl : 4 * cr;
+  char* wtmp;
+  HIPCHK(hipMalloc(reinterpret_cast<void**>(&wtmp), (size_t)Rr * Rr * es));
+  s.W = wtmp;
+  const int G = 64;
+  if (precision == NZE_FP64)
+    hipLaunchKernelGGL(k_theta_only<double>, dim3(G), dim3(NT), 0, st, s, dptm, ltr, G, nullptr, nullptr, 0ull);
+  else
+    hipLaunchKernelGGL(k_theta_only<float>, dim3(G), dim3(NT), 0, st, s, dptm, ltr, G, nullptr, nullptr, 0ull);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipFree(wtmp));
+  HIPCHK(hipFree(tmp));
+  return NZE_OK;
+}
+
+extern "C" int nze_kernel_rowortho(int32_t precision, int32_t R, int32_t C,
+                                   void* X, void* W, double tol_rel,
+                                   double tol_abs, int32_t max_sweeps,
+                                   double* norms, int32_t* sweeps,
+                                   void* stream) {
+  if (precision != NZE_FP64 && precision != NZE_MIXED) return fail(NZE_EINVAL, "precision");
+  if (R < 1 || R > 4 * CHI_LIMIT || C < 4 || (C & 3) || !X || !W || !norms || max_sweeps < 1 || max_sweeps > MAXSW)
+    return fail(NZE_EINVAL, "bad rowortho arguments");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  DevInfo di;
+  int rc = dev_info(di);
+  if (rc) return rc;
+  char* scr;
+  rc = hook_scratch(&scr);
+  if (rc) return rc;
+  double* dscal = reinterpret_cast<double*>(scr);
+  int* dctr = reinterpret_cast<int*>(scr + 256);
+  int* dbar = reinterpret_cast<int*>(scr + 1024);
+  double* dnorm = reinterpret_cast<double*>(scr + 8192);
+  HIPCHK(hipMemsetAsync(scr, 0, 8192, st));
+  Slot s;
+  std::memset(&s, 0, sizeof(s));
+  s.scal = dscal;
+  s.ctr = dctr;
+  s.X = X;
+  s.W = W;
+  s.norms = dnorm;
+  s.tol_rel = tol_rel;
+  s.tol_abs = tol_abs;
+  s.max_sweeps = max_sweeps;
+  const int occ = di.occ[precision == NZE_FP64 ? 0 : 1];
+  const int G = std::max(1, std::min((R + 31) / 32, occ * di.cus));
+  int a_R = R, a_C = C, a_G = G;
+  int* a_bar = dbar;
+  int* a_abort = dbar + 1;
+  unsigned long long a_to = di.timeout_ticks;
+  void* args[] = {&s, &a_R, &a_C, &a_G, &a_bar, &a_abort, &a_to};
+  const void* fn = precision == NZE_FP64 ? reinterpret_cast<const void*>(&k_rowortho<double>)
+                                         : reinterpret_cast<const void*>(&k_rowortho<float>);
+  HIPCHK(hipLaunchCooperativeKernel(fn, dim3(G), dim3(NT), args, 0, st));
+  int ctr[CT_COUNT];
+  HIPCHK(hipMemcpyAsync(ctr, dctr, sizeof(ctr), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(norms, dnorm, (size_t)R * 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (sweeps) *sweeps = ctr[CT_SWTOT];
+  if (ctr[CT_ERR] & ERR_ABORT) return fail(NZE_EHIP, "rowortho aborted at a barrier");
+  if (ctr[CT_ERR] & ERR_NOCONV) return fail(NZE_ENOCONV, "rowortho hit the sweep cap");
+  return NZE_OK;
+}

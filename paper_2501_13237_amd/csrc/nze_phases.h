@@ -1,0 +1,659 @@
+// The phases of one two-site update and of one centre move, as device
+// functions executed by the G workgroups serving one MPO (local index g).
+//
+// Update of the gate on (k, k+1) (Sec. 2.1.2 "Approximate emulation"):
+//   theta   Theta' = (R x 1)(M_k M_{k+1}) written as the row-major matrix X
+//           (rows (a,p'), cols (q',b) left to right; its transpose right to
+//           left), W = I, F2 = ||X||_F^2                         [MFMA]
+//   jacobi  block one-sided Jacobi on the rows of X, accumulating the
+//           rotations in W: afterwards W X has orthogonal rows whose norms
+//           are the singular values                               [MFMA + LDS]
+//   norms   squared row norms in float64
+//   select  sort, truncation rank r, partial fidelity f = kept / total,
+//           emulation fidelity *= f, log-scale, statistics      [one WG]
+//   absorb  left to right: M_k = W rows (U_r), M_{k+1} = X rows / ||kept||
+//           (S_r V_r^T); right to left mirrored
+// Centre move (the canonical form of App. A.1's footnote): the same Jacobi on
+// the centre site viewed as (chi_r x 4 chi_l) (left to right) or
+// (chi_l x 4 chi_r) (right to left), then the orthonormal factor stays and
+// S W is multiplied into the neighbour.
+#ifndef NZE_PHASES_H
+#define NZE_PHASES_H
+
+#include "nze_device.h"
+
+namespace nze {
+
+// ---------------------------------------------------------------- helpers
+
+template <typename T>
+__device__ inline T* site_ptr(const Slot& s, int k) {
+  return reinterpret_cast<T*>(s.sites) + (size_t)k * s.site_cap;
+}
+
+// 64x64-tile GEMM C = A B (row-major, all operands in path precision) over
+// the group's workgroups.  Wave w owns rows [16w, 16w+16) of a tile.
+template <typename T>
+__device__ void gemm_nn(const T* A, int lda, const T* B, int ldb, T* C, int ldc,
+                        int M, int N, int K, int g, int G) {
+  typedef typename AccT<T>::type acc_t;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, kq = lane >> 4;
+  const int tm = (M + 63) / 64, tn = (N + 63) / 64;
+  for (int tile = g; tile < tm * tn; tile += G) {
+    const int m0 = (tile / tn) * 64, n0 = (tile % tn) * 64;
+    const int row = m0 + 16 * w + i;
+    acc_t acc[4];
+    for (int j = 0; j < 4; ++j) acc[j] = acc_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int c = k0 + kq;
+      const T av = (row < M && c < K) ? A[(size_t)row * lda + c] : T(0);
+      for (int j = 0; j < 4; ++j) {
+        const int col = n0 + 16 * j + i;
+        const T bv = (c < K && col < N) ? B[(size_t)c * ldb + col] : T(0);
+        acc[j] = mfma4(av, bv, acc[j]);
+      }
+    }
+    for (int j = 0; j < 4; ++j)
+      for (int r = 0; r < 4; ++r) {
+        const int rr = m0 + 16 * w + mrow<T>(kq, r), cc = n0 + 16 * j + i;
+        if (rr < M && cc < N) C[(size_t)rr * ldc + cc] = acc[j][r];
+      }
+  }
+}
+
+// dst[a][i] = src[perm[i]][a] * scale_i  for a < na, i < r   (LDS transpose)
+// mode 0: scale = cst; 1: cst * sv[i]; 2: cst / sv[i]
+template <typename T>
+__device__ void gather_t(const T* src, int lds, const int* perm, int na, int r,
+                         T* dst, int ldd, const double* sv, int mode,
+                         double cst, int g, int G, double* smem) {
+  T* tile = reinterpret_cast<T*>(smem);   // [32][33]
+  const int ta = (na + 31) / 32, ti = (r + 31) / 32;
+  for (int t = g; t < ta * ti; t += G) {
+    const int a0 = (t / ti) * 32, i0 = (t % ti) * 32;
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += NT) {
+      const int ii = e >> 5, al = e & 31;
+      T v = T(0);
+      if (i0 + ii < r && a0 + al < na) {
+        double sc = cst;
+        if (mode == 1) sc *= sv[i0 + ii];
+        else if (mode == 2) sc /= sv[i0 + ii];
+        v = T(src[(size_t)perm[i0 + ii] * lds + a0 + al] * sc);
+      }
+      tile[ii * 33 + al] = v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += NT) {
+      const int al = e >> 5, ii = e & 31;
+      if (i0 + ii < r && a0 + al < na)
+        dst[(size_t)(a0 + al) * ldd + i0 + ii] = tile[ii * 33 + al];
+    }
+  }
+  __syncthreads();
+}
+
+// dst[i][c] = src[perm[i]][c] * scale_i  for i < r, c < nc
+template <typename T>
+__device__ void gather_r(const T* src, int lds, const int* perm, int r, int nc,
+                         T* dst, int ldd, const double* sv, int mode,
+                         double cst, int g, int G) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = g * 4 + w; i < r; i += 4 * G) {
+    double sc = cst;
+    if (mode == 1) sc *= sv[i];
+    else if (mode == 2) sc /= sv[i];
+    const T* s = src + (size_t)perm[i] * lds;
+    T* d = dst + (size_t)i * ldd;
+    for (int c = lane; c < nc; c += 64) d[c] = T(s[c] * sc);
+  }
+}
+
+// W = I (n x n), distributed by rows.
+template <typename T>
+__device__ void set_identity(T* W, int n, int g, int G) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int r = g * 4 + w; r < n; r += 4 * G)
+    for (int c = lane; c < n; c += 64) W[(size_t)r * n + c] = T(r == c ? 1 : 0);
+}
+
+// ------------------------------------------------------------ theta phase
+
+// X <- (R x 1)(M_k M_{k+1}); also W = I and F2 = ||X||^2.
+template <typename T>
+__device__ void phase_theta(const Slot& s, int k, bool ltr, const double* R,
+                            int g, int G, double* smem) {
+  typedef typename AccT<T>::type acc_t;
+  const int cl = s.dims[k], cm = s.dims[k + 1], cr = s.dims[k + 2];
+  const T* A = site_ptr<T>(s, k);          // (4 cl) x cm
+  const T* B = site_ptr<T>(s, k + 1);      // cm x (4 cr)
+  T* X = reinterpret_cast<T*>(s.X);
+  const int ldb = 4 * cr;
+  const int ldx = ltr ? 4 * cr : 4 * cl;
+  T* tile = reinterpret_cast<T*>(smem);                          // [64][65]
+  double* Rs = smem + (64 * 65 * sizeof(T) + 7) / 8;              // [256]
+  double* red = Rs + 256;                                         // [4]
+  const int tid = threadIdx.x;
+  Rs[tid] = R[tid];
+  const int lane = tid & 63, w = tid >> 6;
+  const int i = lane & 15, kq = lane >> 4;
+  const int ta = (cl + 15) / 16, tb = (cr + 15) / 16;
+  double f2 = 0.0;
+  for (int t = g; t < ta * tb; t += G) {
+    const int a0 = (t / tb) * 16, b0 = (t % tb) * 16;
+    const int row = a0 * 4 + 16 * w + i;
+    const bool rok = row < 4 * cl;
+    const bool cok = b0 + i < cr;
+    acc_t acc[4];
+    for (int q = 0; q < 4; ++q) acc[q] = acc_t{0, 0, 0, 0};
+    for (int c0 = 0; c0 < cm; c0 += 4) {
+      const int c = c0 + kq;
+      const bool kok = c < cm;
+      const T av = (rok && kok) ? A[(size_t)row * cm + c] : T(0);
+      for (int q = 0; q < 4; ++q) {
+        const T bv = (kok && cok) ? B[(size_t)c * ldb + q * cr + b0 + i] : T(0);
+        acc[q] = mfma4(av, bv, acc[q]);
+      }
+    }
+    __syncthreads();
+    for (int q = 0; q < 4; ++q)
+      for (int r = 0; r < 4; ++r)
+        tile[(16 * w + mrow<T>(kq, r)) * 65 + 16 * q + i] = acc[q][r];
+    __syncthreads();
+    int al, bl;
+    if (ltr) { bl = tid & 15; al = tid >> 4; } else { al = tid & 15; bl = tid >> 4; }
+    if (a0 + al < cl && b0 + bl < cr) {
+      T th[16];
+      for (int p = 0; p < 4; ++p)
+        for (int q = 0; q < 4; ++q) th[4 * p + q] = tile[(al * 4 + p) * 65 + q * 16 + bl];
+      const int a = a0 + al, b = b0 + bl;
+      for (int q2 = 0; q2 < 4; ++q2)
+        for (int p2 = 0; p2 < 4; ++p2) {
+          const int P = 4 * p2 + q2;
+          T o = T(0);
+          for (int Q = 0; Q < 16; ++Q) o += T(Rs[P * 16 + Q]) * th[Q];
+          f2 += double(o) * double(o);
+          if (ltr) X[(size_t)(a * 4 + p2) * ldx + q2 * cr + b] = o;
+          else X[(size_t)(q2 * cr + b) * ldx + a * 4 + p2] = o;
+        }
+    }
+  }
+  const double tot = block_sum(f2, red);
+  if (tid == 0 && tot != 0.0) atomicAdd(&s.scal[SC_F2], tot);
+  set_identity(reinterpret_cast<T*>(s.W), ltr ? 4 * cl : 4 * cr, g, G);
+}
+
+// --------------------------------------------------------- Jacobi phase
+
+// LDS layout of one pair step
+struct PairLds {
+  double* Gp;     // [4][1024] per-wave partial Grams
+  double* Gs;     // [32][GLD]
+  double* Qs;     // [32][GLD]
+  double* cs;     // [16]
+  double* sn;     // [16]
+  int* pp;        // [16]
+  int* qq;        // [16]
+  int* rows;      // [32] global row of each pair row (-1 = none)
+  int* flag;      // [2]
+};
+
+__device__ inline PairLds pair_lds(double* smem) {
+  PairLds L;
+  L.Gp = smem;
+  L.Gs = L.Gp + 4 * 1024;
+  L.Qs = L.Gs + 32 * GLD;
+  L.cs = L.Qs + 32 * GLD;
+  L.sn = L.cs + 16;
+  int* ib = reinterpret_cast<int*>(L.sn + 16);
+  L.pp = ib;
+  L.qq = ib + 16;
+  L.rows = ib + 32;
+  L.flag = ib + 64;
+  return L;
+}
+
+// Gs = X_rows X_rows^T (32 x 32) in float64 from MFMA partials.
+template <typename T>
+__device__ void pair_gram(const T* X, int ld, int C, const PairLds& L) {
+  typedef typename AccT<T>::type acc_t;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, kq = lane >> 4;
+  const int r0 = L.rows[i], r1 = L.rows[16 + i];
+  acc_t a00 = {0, 0, 0, 0}, a01 = {0, 0, 0, 0}, a11 = {0, 0, 0, 0};
+  for (int c0 = 16 * w; c0 < C; c0 += 64) {
+    const int c = c0 + 4 * kq;        // C is a multiple of 4
+    T x0[4] = {0, 0, 0, 0}, x1[4] = {0, 0, 0, 0};
+    if (c < C) {
+      if (r0 >= 0) load4(X + (size_t)r0 * ld + c, x0);
+      if (r1 >= 0) load4(X + (size_t)r1 * ld + c, x1);
+    }
+    for (int s = 0; s < 4; ++s) {
+      a00 = mfma4(x0[s], x0[s], a00);
+      a01 = mfma4(x0[s], x1[s], a01);
+      a11 = mfma4(x1[s], x1[s], a11);
+    }
+  }
+  double* P = L.Gp + w * 1024;
+  for (int r = 0; r < 4; ++r) {
+    const int u = mrow<T>(kq, r);
+    P[u * 32 + i] = a00[r];
+    P[u * 32 + 16 + i] = a01[r];
+    P[(16 + u) * 32 + 16 + i] = a11[r];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 1024; e += NT) {
+    const int u = e >> 5, v = e & 31;
+    if (u >= 16 && v < 16) continue;
+    const double val = L.Gp[e] + L.Gp[1024 + e] + L.Gp[2048 + e] + L.Gp[3072 + e];
+    L.Gs[u * GLD + v] = val;
+    if (u < 16 && v >= 16) L.Gs[v * GLD + u] = val;
+  }
+  __syncthreads();
+}
+
+// Eigen-decomposition Gs = Qs diag Qs^T by cyclic parallel Jacobi (16
+// disjoint rotations per step, round-robin ordering), float64, in LDS.
+__device__ void inner_eigh(const PairLds& L) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 32 * 32; e += NT) {
+    const int u = e >> 5, v = e & 31;
+    L.Qs[u * GLD + v] = (u == v) ? 1.0 : 0.0;
+  }
+  double dmax = 0.0;
+  for (int u = 0; u < 32; ++u) dmax = fmax(dmax, L.Gs[u * GLD + u]);
+  const double floor_abs = 1e-30 * dmax;
+  for (int sw = 0; sw < 40; ++sw) {
+    if (tid == 0) L.flag[0] = 0;
+    __syncthreads();
+    for (int step = 0; step < 31; ++step) {
+      if (tid < 16) {
+        const int p = (tid == 0) ? 0 : 1 + ((tid - 1 + step) % 31);
+        const int q = 1 + ((31 - tid - 1 + step) % 31);
+        const double gpp = L.Gs[p * GLD + p], gqq = L.Gs[q * GLD + q];
+        const double gpq = L.Gs[p * GLD + q];
+        double c = 1.0, sn = 0.0;
+        if (fabs(gpq) > floor_abs &&
+            fabs(gpq) > 1e-15 * sqrt(fabs(gpp) * fabs(gqq))) {
+          const double tau = (gqq - gpp) / (2.0 * gpq);
+          const double t = (tau >= 0 ? 1.0 : -1.0) /
+                           (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          sn = t * c;
+          L.flag[0] = 1;
+        }
+        L.cs[tid] = c;
+        L.sn[tid] = sn;
+        L.pp[tid] = p;
+        L.qq[tid] = q;
+      }
+      __syncthreads();
+      {
+        const int P = tid >> 4, P2 = tid & 15;
+        const int p = L.pp[P], q = L.qq[P], p2 = L.pp[P2], q2 = L.qq[P2];
+        const double c = L.cs[P], s = L.sn[P], c2 = L.cs[P2], s2 = L.sn[P2];
+        const double g11 = L.Gs[p * GLD + p2], g12 = L.Gs[p * GLD + q2];
+        const double g21 = L.Gs[q * GLD + p2], g22 = L.Gs[q * GLD + q2];
+        const double h11 = c * g11 - s * g21, h12 = c * g12 - s * g22;
+        const double h21 = s * g11 + c * g21, h22 = s * g12 + c * g22;
+        L.Gs[p * GLD + p2] = c2 * h11 - s2 * h12;
+        L.Gs[p * GLD + q2] = s2 * h11 + c2 * h12;
+        L.Gs[q * GLD + p2] = c2 * h21 - s2 * h22;
+        L.Gs[q * GLD + q2] = s2 * h21 + c2 * h22;
+      }
+      for (int e = tid; e < 512; e += NT) {
+        const int u = e >> 4, P = e & 15;
+        const int p = L.pp[P], q = L.qq[P];
+        const double c = L.cs[P], s = L.sn[P];
+        const double qp = L.Qs[u * GLD + p], qv = L.Qs[u * GLD + q];
+        L.Qs[u * GLD + p] = c * qp - s * qv;
+        L.Qs[u * GLD + q] = s * qp + c * qv;
+      }
+      __syncthreads();
+    }
+    const int f = L.flag[0];
+    __syncthreads();
+    if (!f) break;
+  }
+}
+
+// rows <- Q^T rows for the pair's 32 rows of M (ld, ncols), in place.
+template <typename T>
+__device__ void pair_rotate(T* M, int ld, int ncols, const PairLds& L) {
+  typedef typename AccT<T>::type acc_t;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, kq = lane >> 4;
+  T qa[2][8];
+  for (int h = 0; h < 2; ++h)
+    for (int s = 0; s < 8; ++s) qa[h][s] = T(L.Qs[(4 * s + kq) * GLD + 16 * h + i]);
+  int src[8];
+  for (int s = 0; s < 8; ++s) src[s] = L.rows[4 * s + kq];
+  int dst0[4], dst1[4];
+  for (int r = 0; r < 4; ++r) { dst0[r] = L.rows[mrow<T>(kq, r)]; dst1[r] = L.rows[16 + mrow<T>(kq, r)]; }
+  for (int c0 = 16 * w; c0 < ncols; c0 += 64) {
+    const int c = c0 + i;
+    const bool cok = c < ncols;
+    T xb[8];
+    for (int s = 0; s < 8; ++s)
+      xb[s] = (cok && src[s] >= 0) ? M[(size_t)src[s] * ld + c] : T(0);
+    acc_t d0 = {0, 0, 0, 0}, d1 = {0, 0, 0, 0};
+    for (int s = 0; s < 8; ++s) {
+      d0 = mfma4(qa[0][s], xb[s], d0);
+      d1 = mfma4(qa[1][s], xb[s], d1);
+    }
+    if (cok) {
+      for (int r = 0; r < 4; ++r) {
+        if (dst0[r] >= 0) M[(size_t)dst0[r] * ld + c] = d0[r];
+        if (dst1[r] >= 0) M[(size_t)dst1[r] * ld + c] = d1[r];
+      }
+    }
+  }
+}
+
+// One pair step of sweep `sw`: Gram, convergence test, inner solve, rotate.
+template <typename T>
+__device__ void jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
+                            int J, int nb, int sw, double F2, double* smem) {
+  const PairLds L = pair_lds(smem);
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if (tid < 32) {
+    const int blk = tid < 16 ? I : J;
+    const int r = blk * BW + (tid & 15);
+    L.rows[tid] = (blk < nb && r < R) ? r : -1;
+  }
+  if (tid == 0) L.flag[1] = 0;
+  __syncthreads();
+  pair_gram<T>(X, C, C, L);
+  // convergence test: |g_uv| > tol_rel sqrt(g_uu g_vv) + tol_abs sqrt(F2 max)
+  int need = 0;
+  for (int e = tid; e < 1024; e += NT) {
+    const int u = e >> 5, v = e & 31;
+    if (v <= u) continue;
+    const double guu = L.Gs[u * GLD + u], gvv = L.Gs[v * GLD + v];
+    const double guv = fabs(L.Gs[u * GLD + v]);
+    if (!(guv <= s.tol_rel * sqrt(guu * gvv) +
+                     s.tol_abs * sqrt(F2 * fmax(guu, gvv))))
+      need = 1;
+  }
+  if (need) L.flag[1] = 1;
+  __syncthreads();
+  const int go = L.flag[1];
+  __syncthreads();
+  if (!go) return;
+  if (tid == 0) atomicAdd(&s.ctr[CT_ROT + sw], 1);
+  inner_eigh(L);
+  pair_rotate<T>(X, C, C, L);
+  pair_rotate<T>(W, R, R, L);
+  __syncthreads();
+}
+
+// Round-robin tournament: block at position `pos` in round t (nbe even).
+__device__ inline int tourney_block(int pos, int t, int nbe) {
+  return pos == 0 ? 0 : 1 + ((pos - 1 + t) % (nbe - 1));
+}
+
+template <typename T>
+__device__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, int C, int g,
+                             int G, Group& grp, double* smem) {
+  const int nb = (R + BW - 1) / BW;
+  const int nbe = nb + (nb & 1);
+  const int rounds = nbe - 1, npair = nbe / 2;
+  const double F2 = __hip_atomic_load(&s.scal[SC_F2], __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+  int sweeps = 0;
+  bool conv = false;
+  for (int sw = 0; sw < s.max_sweeps && sw < MAXSW; ++sw) {
+    for (int t = 0; t < rounds; ++t) {
+      for (int q = g; q < npair; q += G) {
+        const int I = tourney_block(q, t, nbe);
+        const int J = tourney_block(nbe - 1 - q, t, nbe);
+        jacobi_pair<T>(s, X, W, R, C, I, J, nb, sw, F2, smem);
+      }
+      if (!group_sync(grp)) return false;
+    }
+    sweeps = sw + 1;
+    const int rot = __hip_atomic_load(&s.ctr[CT_ROT + sw], __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+    if (rot == 0) { conv = true; break; }
+  }
+  if (g == 0 && threadIdx.x == 0) {
+    s.ctr[CT_SWTOT] += sweeps;
+    if (sweeps > s.ctr[CT_MAXSW]) s.ctr[CT_MAXSW] = sweeps;
+    if (!conv) s.ctr[CT_ERR] |= ERR_NOCONV;
+  }
+  return true;
+}
+
+// squared row norms in float64
+template <typename T>
+__device__ void phase_norms(const Slot& s, const T* X, int R, int C, int g,
+                            int G) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int r = g * 4 + w; r < R; r += 4 * G) {
+    double acc = 0.0;
+    const T* x = X + (size_t)r * C;
+    for (int c = lane; c < C; c += 64) acc += double(x[c]) * double(x[c]);
+    acc = wave_sum(acc);
+    if (lane == 0) s.norms[r] = acc;
+  }
+}
+
+// One workgroup: sort the squared norms, pick the rank, update fidelity and
+// log-scale.  gate: truncation rule with chi cap and tie rule; otherwise
+// (centre move) only numerical zeros (s_i <= tau s_1) are dropped.
+__device__ void phase_select(const Slot& s, int R, bool gate, double* smem) {
+  int N = 1;
+  while (N < R) N <<= 1;
+  double* key = smem;
+  int* idx = reinterpret_cast<int*>(smem + N);
+  double* red = smem + N + (N + 1) / 2 + 2;
+  int* sh = reinterpret_cast<int*>(red + 8);
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) {
+    key[i] = i < R ? s.norms[i] : -1.0;
+    idx[i] = i;
+  }
+  __syncthreads();
+  // bitonic sort, decreasing key, ties by increasing index
+  for (int size = 2; size <= N; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < N; i += NT) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool desc = (i & size) == 0;
+          const double ki = key[i], kj = key[j];
+          const int ii = idx[i], ij = idx[j];
+          const bool i_first = ki > kj || (ki == kj && ii < ij);
+          if (desc ? !i_first : i_first) {
+            key[i] = kj; key[j] = ki; idx[i] = ij; idx[j] = ii;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  double tot = 0.0;
+  for (int i = tid; i < R; i += NT) tot += fmax(key[i], 0.0);
+  tot = block_sum(tot, red);
+  const double s1 = sqrt(fmax(key[0], 0.0));
+  int above = 0;
+  for (int i = tid; i < R; i += NT) above += (sqrt(fmax(key[i], 0.0)) > s.tau * s1) ? 1 : 0;
+  above = (int)block_sum((double)above, red);
+  if (tid == 0) {
+    int r;
+    if (!(s1 > 0.0)) {
+      r = 1;
+    } else if (gate) {
+      r = above < s.chi ? above : s.chi;
+      if (r < 1) r = 1;
+      if (r == s.chi && r < above) {
+        const int r0 = r;
+        while (r > 0) {
+          const double a = sqrt(fmax(key[r - 1], 0.0)), b = sqrt(fmax(key[r], 0.0));
+          if (a - b <= s.tie * a) --r; else break;
+        }
+        if (r == 0) r = r0;
+      }
+    } else {
+      r = above < 1 ? 1 : above;
+    }
+    sh[0] = r;
+  }
+  __syncthreads();
+  const int r = sh[0];
+  double kept = 0.0;
+  for (int i = tid; i < r; i += NT) {
+    kept += fmax(key[i], 0.0);
+    s.perm[i] = idx[i];
+    s.sval[i] = sqrt(fmax(key[i], 0.0));
+  }
+  kept = block_sum(kept, red);
+  if (tid == 0) {
+    s.ctr[CT_RANK] = r;
+    s.scal[SC_KEPT] = kept;
+    if (!(tot == tot) || tot > 1e300 || !(kept > 0.0)) s.ctr[CT_ERR] |= ERR_NAN;
+    if (gate) {
+      const double f = kept / tot;
+      s.scal[SC_FID] *= f;
+      s.scal[SC_LOG] += 0.5 * log(kept);
+      s.scal[SC_MAXDISC] = fmax(s.scal[SC_MAXDISC], 1.0 - f);
+      if (r < R && key[r] > 0.0) {
+        const double gap = (sqrt(key[r - 1]) - sqrt(key[r])) / s1;
+        s.scal[SC_MINGAP] = fmin(s.scal[SC_MINGAP], gap);
+      }
+      s.ctr[CT_UPD] += 1;
+    }
+    s.scal[SC_F2] = 0.0;
+  }
+  for (int i = tid; i < MAXSW; i += NT) s.ctr[CT_ROT + i] = 0;
+}
+
+// ----------------------------------------------------------- full ops
+
+template <typename T>
+__device__ bool op_gate(const Slot& s, int k, bool ltr, const double* R, int g,
+                        int G, Group& grp, double* smem) {
+  const int cl = s.dims[k], cr = s.dims[k + 2];
+  const int Rr = ltr ? 4 * cl : 4 * cr, Cc = ltr ? 4 * cr : 4 * cl;
+  T* X = reinterpret_cast<T*>(s.X);
+  T* W = reinterpret_cast<T*>(s.W);
+  phase_theta<T>(s, k, ltr, R, g, G, smem);
+  if (!group_sync(grp)) return false;
+  if (!phase_jacobi<T>(s, X, W, Rr, Cc, g, G, grp, smem)) return false;
+  phase_norms<T>(s, X, Rr, Cc, g, G);
+  if (!group_sync(grp)) return false;
+  if (g == 0) phase_select(s, Rr, true, smem);
+  if (!group_sync(grp)) return false;
+  const int r = s.ctr[CT_RANK];
+  const double inv = 1.0 / sqrt(s.scal[SC_KEPT]);
+  T* Mk = site_ptr<T>(s, k);
+  T* Mk1 = site_ptr<T>(s, k + 1);
+  if (ltr) {
+    gather_t<T>(W, Rr, s.perm, 4 * cl, r, Mk, r, nullptr, 0, 1.0, g, G, smem);
+    gather_r<T>(X, Cc, s.perm, r, 4 * cr, Mk1, 4 * cr, nullptr, 0, inv, g, G);
+  } else {
+    gather_t<T>(X, Cc, s.perm, 4 * cl, r, Mk, r, nullptr, 0, inv, g, G, smem);
+    gather_r<T>(W, Rr, s.perm, r, 4 * cr, Mk1, 4 * cr, nullptr, 0, 1.0, g, G);
+  }
+  if (!group_sync(grp)) return false;
+  if (g == 0 && threadIdx.x == 0) s.dims[k + 1] = r;
+  return group_sync(grp);
+}
+
+// Centre move away from site c: to c+1 (ltr) or c-1.
+template <typename T>
+__device__ bool op_move(const Slot& s, int c, bool ltr, int g, int G,
+                        Group& grp, double* smem) {
+  const int cl = s.dims[c], cr = s.dims[c + 1];
+  T* X = reinterpret_cast<T*>(s.X);
+  T* W = reinterpret_cast<T*>(s.W);
+  T* Rm = reinterpret_cast<T*>(s.Rm);
+  T* M = site_ptr<T>(s, c);
+  const int Rr = ltr ? cr : cl, Cc = ltr ? 4 * cl : 4 * cr;
+  // X = M^T (chi_r x 4 chi_l) or M (chi_l x 4 chi_r); F2
+  {
+    double f2 = 0.0;
+    if (ltr) {
+      T* tile = reinterpret_cast<T*>(smem);
+      const int na = 4 * cl;   // rows of M
+      const int ta = (na + 31) / 32, tj = (cr + 31) / 32;
+      for (int t = g; t < ta * tj; t += G) {
+        const int a0 = (t / tj) * 32, j0 = (t % tj) * 32;
+        __syncthreads();
+        for (int e = threadIdx.x; e < 1024; e += NT) {
+          const int al = e >> 5, jl = e & 31;
+          T v = T(0);
+          if (a0 + al < na && j0 + jl < cr) v = M[(size_t)(a0 + al) * cr + j0 + jl];
+          tile[al * 33 + jl] = v;
+          f2 += double(v) * double(v);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 1024; e += NT) {
+          const int jl = e >> 5, al = e & 31;
+          if (a0 + al < na && j0 + jl < cr)
+            X[(size_t)(j0 + jl) * na + a0 + al] = tile[al * 33 + jl];
+        }
+      }
+      __syncthreads();
+    } else {
+      const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+      for (int r = g * 4 + w; r < cl; r += 4 * G)
+        for (int cc = lane; cc < Cc; cc += 64) {
+          const T v = M[(size_t)r * Cc + cc];
+          X[(size_t)r * Cc + cc] = v;
+          f2 += double(v) * double(v);
+        }
+    }
+    double* red = smem + 2048;
+    const double tot = block_sum(f2, red);
+    if (threadIdx.x == 0 && tot != 0.0) atomicAdd(&s.scal[SC_F2], tot);
+    set_identity(W, Rr, g, G);
+  }
+  if (!group_sync(grp)) return false;
+  if (!phase_jacobi<T>(s, X, W, Rr, Cc, g, G, grp, smem)) return false;
+  phase_norms<T>(s, X, Rr, Cc, g, G);
+  if (!group_sync(grp)) return false;
+  if (g == 0) phase_select(s, Rr, false, smem);
+  if (!group_sync(grp)) return false;
+  const int r = s.ctr[CT_RANK];
+  if (ltr) {
+    // M_c = Y^T S^-1 (4cl x r);  Rm = S W_perm (r x cr)
+    gather_t<T>(X, Cc, s.perm, 4 * cl, r, M, r, s.sval, 2, 1.0, g, G, smem);
+    gather_r<T>(W, Rr, s.perm, r, cr, Rm, cr, s.sval, 1, 1.0, g, G);
+  } else {
+    // M_c = S^-1 Y (r x 4cr);  Lm = W_perm^T S (cl x r)
+    gather_r<T>(X, Cc, s.perm, r, 4 * cr, M, 4 * cr, s.sval, 2, 1.0, g, G);
+    gather_t<T>(W, Rr, s.perm, cl, r, Rm, r, s.sval, 1, 1.0, g, G, smem);
+  }
+  if (!group_sync(grp)) return false;
+  if (ltr) {
+    const int c2 = s.dims[c + 2];
+    T* Mn = site_ptr<T>(s, c + 1);          // cr x 4c2
+    gemm_nn<T>(Rm, cr, Mn, 4 * c2, X, 4 * c2, r, 4 * c2, cr, g, G);
+    if (!group_sync(grp)) return false;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int i = g * 4 + w; i < r; i += 4 * G)
+      for (int cc = lane; cc < 4 * c2; cc += 64)
+        Mn[(size_t)i * 4 * c2 + cc] = X[(size_t)i * 4 * c2 + cc];
+    if (!group_sync(grp)) return false;
+    if (g == 0 && threadIdx.x == 0) s.dims[c + 1] = r;
+  } else {
+    const int c0 = s.dims[c - 1];
+    T* Mp = site_ptr<T>(s, c - 1);          // 4c0 x cl
+    gemm_nn<T>(Mp, cl, Rm, r, X, r, 4 * c0, r, cl, g, G);
+    if (!group_sync(grp)) return false;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int i = g * 4 + w; i < 4 * c0; i += 4 * G)
+      for (int cc = lane; cc < r; cc += 64)
+        Mp[(size_t)i * r + cc] = X[(size_t)i * r + cc];
+    if (!group_sync(grp)) return false;
+    if (g == 0 && threadIdx.x == 0) s.dims[c] = r;
+  }
+  return group_sync(grp);
+}
+
+}  // namespace nze
+
+#endif

@@ -1,0 +1,341 @@
+"""Thin ctypes binding of ``libnze.so`` (declared in ``include/nze.h``).
+
+Argument marshalling only: every step of the emulation runs in the library.
+PyTorch provides the device workspace and the stream; nothing else.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnze.so")
+
+NZE_OK, NZE_EINVAL, NZE_ENOMEM, NZE_EHIP, NZE_ENOCONV, NZE_EFIT, NZE_ENUM = \
+    0, -1, -2, -3, -4, -5, -6
+NZE_FP64, NZE_MIXED = 0, 1
+NZE_POLY, NZE_EXP3, NZE_LOGLIN_W = 0, 1, 2
+
+c_double_p = ctypes.POINTER(ctypes.c_double)
+c_int32_p = ctypes.POINTER(ctypes.c_int32)
+c_uint8_p = ctypes.POINTER(ctypes.c_uint8)
+
+
+class NzeNoise(ctypes.Structure):
+    _fields_ = [("dep", ctypes.c_double), ("ad", ctypes.c_double),
+                ("px", ctypes.c_double), ("py", ctypes.c_double),
+                ("pz", ctypes.c_double)]
+
+
+class MpoConfig(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("chi_max", ctypes.c_int32),
+                ("n_levels", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("trunc_tol", ctypes.c_double), ("tie_tol", ctypes.c_double),
+                ("jacobi_tol", ctypes.c_double),
+                ("max_sweeps", ctypes.c_int32), ("block", ctypes.c_int32)]
+
+
+class NzeStats(ctypes.Structure):
+    _fields_ = [("fidelity", ctypes.c_double), ("log_scale", ctypes.c_double),
+                ("max_discarded", ctypes.c_double),
+                ("min_cut_gap", ctypes.c_double),
+                ("max_bond", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("updates", ctypes.c_int64), ("sweeps_total", ctypes.c_int64)]
+
+
+class NzeFitOpts(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int32), ("delta_f", ctypes.c_double),
+                ("delta_d", ctypes.c_double), ("small", ctypes.c_double),
+                ("dip_threshold", ctypes.c_double),
+                ("ref_sign", ctypes.c_int32), ("b_max", ctypes.c_double)]
+
+
+class NzeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nze error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "paper_2501_13237_amd.build.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    L.nze_build_ptm.argtypes = [c_double_p, c_double_p,
+                                ctypes.POINTER(NzeNoise), ctypes.c_double,
+                                c_double_p]
+    L.mpo_footprint.argtypes = [ctypes.POINTER(MpoConfig)]
+    L.mpo_footprint.restype = ctypes.c_size_t
+    L.mpo_init.argtypes = [ctypes.POINTER(ctypes.c_void_p),
+                           ctypes.POINTER(MpoConfig), c_double_p,
+                           ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    L.mpo_free.argtypes = [ctypes.c_void_p]
+    L.mpo_free.restype = None
+    L.mpo_apply_layer.argtypes = [ctypes.c_void_p, ctypes.c_int32, c_int32_p,
+                                  c_double_p]
+    L.mpo_apply_layer_batch.argtypes = [
+        ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, c_int32_p,
+        ctypes.POINTER(c_int32_p), ctypes.POINTER(c_double_p)]
+    L.mpo_expect.argtypes = [ctypes.c_void_p, ctypes.c_int32, c_uint8_p,
+                             c_double_p, c_double_p, c_double_p]
+    L.mpo_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(NzeStats),
+                            c_int32_p]
+    L.mpo_bond_spectrum.argtypes = [ctypes.c_void_p, ctypes.c_int32,
+                                    ctypes.c_int32, c_double_p, ctypes.c_int32,
+                                    c_int32_p]
+    L.mpo_sync.argtypes = [ctypes.c_void_p]
+    L.nze_kernel_theta.argtypes = [ctypes.c_int32] * 4 + [
+        ctypes.c_void_p, ctypes.c_void_p, c_double_p, ctypes.c_int32,
+        ctypes.c_void_p, ctypes.c_void_p]
+    L.nze_kernel_rowortho.argtypes = [
+        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+        c_double_p, c_int32_p, ctypes.c_void_p]
+    L.nze_fit_opts_default.argtypes = [ctypes.POINTER(NzeFitOpts)]
+    L.nze_fit_opts_default.restype = None
+    L.nze_extrapolate.argtypes = [ctypes.c_int32, c_double_p, c_double_p,
+                                  c_double_p, ctypes.c_double, ctypes.c_int32,
+                                  ctypes.POINTER(NzeFitOpts), c_double_p,
+                                  c_double_p, c_uint8_p, c_int32_p]
+    L.nze_fidelity_extrapolate.argtypes = [ctypes.c_int32, c_double_p,
+                                           c_double_p, c_double_p, c_int32_p]
+    for fn in ("nze_strerror",):
+        getattr(L, fn).argtypes = [ctypes.c_int]
+        getattr(L, fn).restype = ctypes.c_char_p
+    for fn in ("nze_last_error", "nze_version"):
+        getattr(L, fn).argtypes = []
+        getattr(L, fn).restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != NZE_OK:
+        raise NzeError(rc, lib().nze_last_error().decode())
+    return rc
+
+
+def _dp(a):
+    return a.ctypes.data_as(c_double_p)
+
+
+# ------------------------------------------------------------------ PTMs
+
+
+def noise_struct(noise):
+    """noise: dict with any of dep, ad, px, py, pz (or None)."""
+    noise = noise or {}
+    return NzeNoise(noise.get("dep", 0.0), noise.get("ad", 0.0),
+                    noise.get("px", 0.0), noise.get("py", 0.0),
+                    noise.get("pz", 0.0))
+
+
+def build_ptm(U, noise=None, scale=1.0):
+    U = np.asarray(U, dtype=np.complex128)
+    re = np.ascontiguousarray(U.real)
+    im = np.ascontiguousarray(U.imag)
+    out = np.empty((16, 16))
+    nz = noise_struct(noise)
+    _check(lib().nze_build_ptm(_dp(re), _dp(im), ctypes.byref(nz),
+                               float(scale), _dp(out)))
+    return out
+
+
+def layer_ptms(unitaries, noise, factors):
+    """[L][n_gates][16][16] PTMs of one layer at every level factor."""
+    out = np.empty((len(factors), len(unitaries), 16, 16))
+    for j, c in enumerate(factors):
+        for i, U in enumerate(unitaries):
+            out[j, i] = build_ptm(U, noise, c)
+    return out
+
+
+# ------------------------------------------------------------------ fits
+
+
+def fit_opts(**kw):
+    o = NzeFitOpts()
+    lib().nze_fit_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def extrapolate(lam, values, fidelity=None, lam_target=0.0, method=NZE_POLY,
+                **opts):
+    """Returns (value, coef[3], used_mask, method_used)."""
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    val = np.ascontiguousarray(values, dtype=np.float64)
+    fid = None if fidelity is None else np.ascontiguousarray(fidelity,
+                                                             dtype=np.float64)
+    out = ctypes.c_double()
+    coef = np.zeros(3)
+    used = np.zeros(lam.size, dtype=np.uint8)
+    mu = ctypes.c_int32()
+    o = fit_opts(**opts)
+    _check(lib().nze_extrapolate(lam.size, _dp(lam), _dp(val),
+                                 None if fid is None else _dp(fid),
+                                 float(lam_target), method, ctypes.byref(o),
+                                 ctypes.byref(out), _dp(coef),
+                                 used.ctypes.data_as(c_uint8_p),
+                                 ctypes.byref(mu)))
+    return out.value, coef, used.astype(bool), mu.value
+
+
+def fidelity_extrapolate(values, fids):
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    f = np.ascontiguousarray(fids, dtype=np.float64)
+    out = ctypes.c_double()
+    conv = ctypes.c_int32()
+    _check(lib().nze_fidelity_extrapolate(v.size, _dp(v), _dp(f),
+                                          ctypes.byref(out),
+                                          ctypes.byref(conv)))
+    return out.value, bool(conv.value)
+
+
+# ------------------------------------------------------ kernel-level hooks
+
+
+def kernel_theta(A, B, ptm16, ltr=True):
+    """Theta' of one two-site update from device tensors A ((4cl) x cm) and
+    B (cm x (4cr)) in the path precision (torch float64 or float32)."""
+    import torch
+    prec = NZE_FP64 if A.dtype == torch.float64 else NZE_MIXED
+    cl, cm = A.shape[0] // 4, A.shape[1]
+    cr = B.shape[1] // 4
+    X = torch.empty((4 * cl, 4 * cr) if ltr else (4 * cr, 4 * cl),
+                    dtype=A.dtype, device=A.device)
+    p = np.ascontiguousarray(ptm16, dtype=np.float64)
+    _check(lib().nze_kernel_theta(prec, cl, cm, cr, A.data_ptr(), B.data_ptr(),
+                                  _dp(p), int(ltr), X.data_ptr(),
+                                  torch.cuda.current_stream().cuda_stream))
+    return X
+
+
+def kernel_rowortho(X, tol_rel, tol_abs, max_sweeps=30):
+    """Block one-sided Jacobi on the rows of the device matrix X (in place);
+    returns (W, squared row norms, sweeps)."""
+    import torch
+    prec = NZE_FP64 if X.dtype == torch.float64 else NZE_MIXED
+    R, C = X.shape
+    W = torch.empty((R, R), dtype=X.dtype, device=X.device)
+    norms = np.zeros(R)
+    sw = ctypes.c_int32()
+    _check(lib().nze_kernel_rowortho(prec, R, C, X.data_ptr(), W.data_ptr(),
+                                     tol_rel, tol_abs, max_sweeps, _dp(norms),
+                                     ctypes.byref(sw),
+                                     torch.cuda.current_stream().cuda_stream))
+    return W, norms, sw.value
+
+
+# ------------------------------------------------------------------- MPOs
+
+
+def make_config(n, chi, levels, precision=NZE_FP64, trunc_tol=0.0,
+                tie_tol=0.0, jacobi_tol=0.0, max_sweeps=0, block=0):
+    return MpoConfig(n, chi, levels, precision, trunc_tol, tie_tol,
+                     jacobi_tol, max_sweeps, block)
+
+
+def footprint(cfg):
+    return int(lib().mpo_footprint(ctypes.byref(cfg)))
+
+
+class MPO:
+    """L vectorised MPOs (one per noise level) resident on the current GPU.
+
+    The device workspace is a torch uint8 tensor owned by this object; the
+    stream is torch's current stream unless one is given.
+    """
+
+    def __init__(self, n, chi, levels, precision=NZE_FP64, init_sites=None,
+                 stream=None, **cfg_kw):
+        import torch
+        self.cfg = make_config(n, chi, levels, precision, **cfg_kw)
+        nbytes = footprint(self.cfg)
+        if nbytes == 0:
+            raise NzeError(NZE_EINVAL, "invalid configuration")
+        self.nbytes = nbytes
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self.ws.data_ptr()
+        ptr = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.n, self.chi, self.levels = n, chi, levels
+        h = ctypes.c_void_p()
+        init = None
+        if init_sites is not None:
+            init = np.ascontiguousarray(init_sites, dtype=np.float64)
+        _check(lib().mpo_init(ctypes.byref(h), ctypes.byref(self.cfg),
+                              None if init is None else _dp(init),
+                              ctypes.c_void_p(ptr), ctypes.c_size_t(nbytes),
+                              ctypes.c_void_p(self.stream.cuda_stream)))
+        self.h = h
+
+    def apply_layer(self, left_sites, ptms):
+        ls = np.ascontiguousarray(left_sites, dtype=np.int32)
+        p = np.ascontiguousarray(ptms, dtype=np.float64)
+        assert p.shape == (self.levels, ls.size, 16, 16)
+        _check(lib().mpo_apply_layer(self.h, ls.size,
+                                     ls.ctypes.data_as(c_int32_p), _dp(p)))
+
+    def expect(self, observables):
+        obs = np.ascontiguousarray(np.asarray(observables, dtype=np.uint8)
+                                   .reshape(-1, self.n))
+        vals = np.zeros((self.levels, obs.shape[0]))
+        fid = np.zeros(self.levels)
+        tr = np.zeros(self.levels)
+        _check(lib().mpo_expect(self.h, obs.shape[0],
+                                obs.ctypes.data_as(c_uint8_p), _dp(vals),
+                                _dp(fid), _dp(tr)))
+        return vals, fid, tr
+
+    def stats(self):
+        st = (NzeStats * self.levels)()
+        bonds = np.zeros((self.levels, self.n - 1), dtype=np.int32)
+        _check(lib().mpo_stats(self.h, st, bonds.ctypes.data_as(c_int32_p)))
+        return [dict(fidelity=s.fidelity, log_scale=s.log_scale,
+                     max_discarded=s.max_discarded,
+                     min_cut_gap=s.min_cut_gap, max_bond=s.max_bond,
+                     max_sweeps=s.max_sweeps, updates=s.updates,
+                     sweeps_total=s.sweeps_total) for s in st], bonds
+
+    def sync(self):
+        _check(lib().mpo_sync(self.h))
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            lib().mpo_free(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def apply_layer_batch(mpos, left_sites_list, ptms_list):
+    """Advance several MPO handles by one layer each in shared launches."""
+    k = len(mpos)
+    hs = (ctypes.c_void_p * k)(*[m.h.value for m in mpos])
+    ls_arrs = [np.ascontiguousarray(x, dtype=np.int32) for x in left_sites_list]
+    p_arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in ptms_list]
+    ng = np.array([a.size for a in ls_arrs], dtype=np.int32)
+    lsp = (c_int32_p * k)(*[a.ctypes.data_as(c_int32_p) for a in ls_arrs])
+    pp = (c_double_p * k)(*[_dp(a) for a in p_arrs])
+    _check(lib().mpo_apply_layer_batch(hs, k, ng.ctypes.data_as(c_int32_p),
+                                       lsp, pp))
+
+
+def run_circuit(mpo, layers, noise, factors):
+    """Apply every layer of ``layers`` (list of (left_sites, unitaries)) at all
+    level factors."""
+    for ls, us in layers:
+        mpo.apply_layer(ls, layer_ptms(us, noise, factors))

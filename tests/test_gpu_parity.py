@@ -1,0 +1,168 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle on the same
+seeded inputs.  Only gauge-invariant outputs are compared: expectation values,
+emulation fidelity, trace, bond dimensions where nothing is truncated."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mpo as ompo
+from oracle import pauliprop, ptm
+from paper_2501_13237_amd import nze, workloads
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle_run(n, layers, noise, factors, chi, tau=1e-14, tie=1e-10):
+    out = []
+    for c in factors:
+        nz = ptm.Noise(**noise).scaled(c)
+        m = ompo.PauliMPO(n, chi, tau=tau, tie_tol=tie)
+        for ls, us in layers:
+            m.apply_layer(ls, [ptm.ptm_noisy_gate(U, nz) for U in us])
+        out.append(m)
+    return out
+
+
+def _gpu_run(n, layers, noise, factors, chi, precision, **kw):
+    m = nze.MPO(n, chi, len(factors), precision, **kw)
+    nze.run_circuit(m, layers, noise, factors)
+    return m
+
+
+def _compare(n, layers, noise, factors, chi, obs, precision, tol, **kw):
+    _say(f"case n={n} depth={len(layers)} chi={chi} L={len(factors)} "
+         f"prec={precision} noise={noise}")
+    g = _gpu_run(n, layers, noise, factors, chi, precision, **kw)
+    vals, fid, tr = g.expect(obs)
+    orc = _oracle_run(n, layers, noise, factors, chi,
+                      tie=(1e-10 if precision == nze.NZE_FP64 else 1e-5))
+    for j, m in enumerate(orc):
+        ref = m.expectations(obs)
+        err = np.max(np.abs(vals[j] - ref))
+        _say(f"  level {j}: max|dO|={err:.3e} F_gpu={fid[j]:.12f} "
+             f"F_orc={m.fidelity:.12f} tr_gpu={tr[j]:.12f} tr_orc={m.trace():.12f}")
+        assert err < tol
+        assert abs(fid[j] - m.fidelity) < tol * max(1.0, m.fidelity)
+        assert abs(tr[j] - m.trace()) < 10 * tol
+    return g, orc
+
+
+@pytest.mark.parametrize("precision,tol", [(nze.NZE_FP64, FP64_TOL),
+                                           (nze.NZE_MIXED, MIXED_TOL)])
+def test_plain_n8_exact(precision, tol):
+    w = workloads.plain_fp64_n8(seed=0)
+    layers = w.circuit()
+    g, orc = _compare(w.n, layers, w.noise, w.factors, w.chi, w.observables,
+                      precision, tol)
+    stats, bonds = g.stats()
+    assert all(abs(s["fidelity"] - 1.0) < tol for s in stats)
+    assert np.all(bonds == np.array(orc[0].bond_dims())[None, :]) or \
+        precision == nze.NZE_MIXED
+
+
+def test_small_chain_two_sites():
+    layers = workloads.brickwork(2, 3, seed=5)
+    obs = workloads.weight1_all(2) + workloads.weight2_neighbours(2)
+    _compare(2, layers, {"dep": 0.05}, [1.0, 2.0], 4, obs, nze.NZE_FP64,
+             FP64_TOL)
+
+
+@pytest.mark.parametrize("chi", [16, 20])
+def test_truncated_fp64(chi):
+    n = 10
+    layers = workloads.brickwork(n, 10, seed=3)
+    obs = workloads.z_singles(n) + workloads.zz_neighbours(n)
+    g, orc = _compare(n, layers, {"dep": 1e-2}, [1.0, 4.0], chi, obs,
+                      nze.NZE_FP64, FP64_TOL)
+    assert orc[0].fidelity < 0.999
+
+
+def test_odd_chain_ragged_amplitude_damping():
+    n = 7
+    layers = workloads.brickwork(n, 9, seed=8)
+    obs = workloads.weight1_all(n)
+    _compare(n, layers, {"dep": 2e-3, "ad": 5e-3}, [1.0, 3.0, 5.0], 40, obs,
+             nze.NZE_FP64, FP64_TOL)
+
+
+def test_chi_one_product_truncation():
+    n = 6
+    layers = workloads.brickwork(n, 4, seed=2)
+    obs = workloads.z_singles(n)
+    _compare(n, layers, {"dep": 0.05}, [1.0], 1, obs, nze.NZE_FP64, FP64_TOL)
+
+
+def test_mixed_truncated_ad():
+    n = 12
+    layers = workloads.brickwork(n, 10, seed=4)
+    obs = workloads.z_singles(n)
+    _compare(n, layers, {"dep": 1e-3, "ad": 5e-4}, [1.0], 32, obs,
+             nze.NZE_MIXED, MIXED_TOL)
+
+
+def test_clifford_exact_vs_pauli_propagation():
+    n = 16
+    layers = workloads.brickwork(n, 4, seed=6, kind="clifford")
+    noise = {"px": 3e-3, "py": 3e-3, "pz": 3e-3}
+    obs = workloads.weight1_all(n) + workloads.weight2_neighbours(n)
+    for prec, tol in ((nze.NZE_FP64, FP64_TOL), (nze.NZE_MIXED, MIXED_TOL)):
+        _say(f"clifford prec={prec}")
+        g = _gpu_run(n, layers, noise, [1.0, 4.0], 256, prec)
+        vals, fid, tr = g.expect(obs)
+        gates = [(k, U) for ls, us in layers for k, U in zip(ls, us)]
+        for j, c in enumerate([1.0, 4.0]):
+            nz = ptm.Noise(**noise).scaled(c)
+            ref = np.array([pauliprop.expectation(n, gates, nz, o) for o in obs])
+            err = np.max(np.abs(vals[j] - ref))
+            _say(f"  level {j}: max err vs Pauli propagation {err:.3e}")
+            assert err < tol
+            assert abs(fid[j] - 1.0) < tol
+
+
+def test_batch_matches_separate_bitwise():
+    n = 10
+    la = workloads.brickwork(n, 6, seed=11)
+    lb = workloads.brickwork(n + 2, 5, seed=12)
+    obs_a = workloads.z_singles(n)
+    obs_b = workloads.z_singles(n + 2)
+    noise = {"dep": 5e-3}
+    sep_a = _gpu_run(n, la, noise, [1.0, 2.0], 16, nze.NZE_FP64)
+    sep_b = _gpu_run(n + 2, lb, noise, [1.0], 16, nze.NZE_FP64)
+    ma = nze.MPO(n, 16, 2, nze.NZE_FP64)
+    mb = nze.MPO(n + 2, 16, 1, nze.NZE_FP64)
+    for t in range(max(len(la), len(lb))):
+        mpos, lss, ptms = [], [], []
+        if t < len(la):
+            mpos.append(ma)
+            lss.append(la[t][0])
+            ptms.append(nze.layer_ptms(la[t][1], noise, [1.0, 2.0]))
+        if t < len(lb):
+            mpos.append(mb)
+            lss.append(lb[t][0])
+            ptms.append(nze.layer_ptms(lb[t][1], noise, [1.0]))
+        nze.apply_layer_batch(mpos, lss, ptms)
+    va, fa, _ = ma.expect(obs_a)
+    vb, fb, _ = mb.expect(obs_b)
+    ra, rfa, _ = sep_a.expect(obs_a)
+    rb, rfb, _ = sep_b.expect(obs_b)
+    assert np.array_equal(va, ra) and np.array_equal(fa, rfa)
+    assert np.array_equal(vb, rb) and np.array_equal(fb, rfb)
+
+
+def test_invalid_layer_rejected():
+    m = nze.MPO(6, 8, 1, nze.NZE_FP64)
+    with pytest.raises(nze.NzeError) as e:
+        m.apply_layer(np.array([2, 1], dtype=np.int32), np.zeros((1, 2, 16, 16)))
+    assert e.value.code == nze.NZE_EINVAL
+    with pytest.raises(nze.NzeError) as e:
+        m.apply_layer(np.array([5], dtype=np.int32), np.zeros((1, 1, 16, 16)))
+    assert e.value.code == nze.NZE_EINVAL
