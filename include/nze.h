@@ -96,9 +96,13 @@ typedef struct mpo_config {
                           0 -> 1e-14 (FP64) / 1e-7 (mixed)                   */
   double tie_tol;      /* relative tie tolerance at a chi cut (a tied cluster
                           is dropped whole); 0 -> 1e-10 (FP64) / 1e-5 (mixed)*/
-  double jacobi_tol;   /* off-diagonal convergence threshold of the one-sided
-                          Jacobi SVD; 0 -> 1e-13 (FP64) / 2e-6 (mixed)        */
-  int32_t max_sweeps;  /* Jacobi sweep cap; 0 -> 20 (FP64) / 14 (mixed)       */
+  double jacobi_tol;   /* relative off-diagonal threshold of the one-sided
+                          Jacobi SVD: rows u, v count as orthogonal when
+                          |<x_u,x_v>| <= tol |x_u||x_v| + tol_abs |X| |x_max|;
+                          tol is raised to at least 8 sqrt(C) eps of the path
+                          (C = row length); 0 -> 1e-13 (FP64) / 2e-6 (mixed);
+                          tol_abs is 1e-15 (FP64) / 1e-6 (mixed)             */
+  int32_t max_sweeps;  /* Jacobi sweep cap (<= 40); 0 -> 30                   */
   int32_t block;       /* Jacobi row-block width b (pairs are 2b rows);
                           0 -> chosen by the built-in tuner                   */
 } mpo_config;
@@ -174,11 +178,26 @@ typedef struct nze_stats {
   int32_t max_sweeps;    /* most Jacobi sweeps any SVD needed                 */
   int64_t updates;       /* two-site updates applied so far                   */
   int64_t sweeps_total;  /* Jacobi sweeps over all updates and centre moves   */
+  double flops;          /* algorithmic flops executed so far: contraction
+                            32 cl cm cr + superoperator 512 cl cr per update;
+                            per Jacobi sweep on R rows of length C,
+                            4 R^2 (2C + R) (block Grams plus rotation of the
+                            data and of the accumulator); centre-move
+                            absorption 8 r cr c2                             */
 } nze_stats;
 
 /* Per-level statistics (synchronises the stream).
  *   stats : [n_levels] out.   bonds : [n_levels][n-1] int32 out or NULL. */
 int mpo_stats(mpo_t* h, nze_stats* stats, int32_t* bonds);
+
+/* Diagnostics: time spent by workgroup 0 of each level in the phases of the
+ * layer kernel, in milliseconds, [n_levels][16]: contraction, block Gram,
+ * convergence test, LDS eigen-solve, rotation of the data, rotation of the
+ * accumulator, barrier wait inside Jacobi, row norms, selection, absorption,
+ * centre-move preparation, centre-move absorption, then (not times) inner
+ * Jacobi sweeps and pair solves counted, then 0, then whole-Jacobi time.
+ * Synchronises the stream. */
+int mpo_profile(mpo_t* h, double* ms_out);
 
 /* Schmidt values across bond (l, l+1) of level lv (App. A.1: canonical form
  * at that bond; used for the MPO entanglement entropy).

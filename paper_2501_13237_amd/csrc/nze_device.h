@@ -16,13 +16,14 @@ constexpr int GLD = 33;          // LDS leading dimension of 32x32 fp64 tiles
 constexpr int MAXSW = 40;        // sweep-counter slots
 constexpr int CHI_LIMIT = 512;   // largest chi_max (select sorts 4*chi keys)
 constexpr int SMEM_DOUBLES = 6400;
+constexpr int INNER_SWEEPS = 1;  // cyclic sweeps of the LDS solve per pair visit
 
 enum { OP_NONE = 0, OP_GATE_LR = 1, OP_GATE_RL = 2, OP_MOVE_LR = 3,
        OP_MOVE_RL = 4 };
 
 // per-MPO float64 scalars
 enum { SC_LOG = 0, SC_FID = 1, SC_MAXDISC = 2, SC_MINGAP = 3, SC_F2 = 4,
-       SC_KEPT = 5, SC_COUNT = 8 };
+       SC_KEPT = 5, SC_FLOPS = 6, SC_COUNT = 8 };
 // per-MPO int counters
 enum { CT_RANK = 0, CT_ERR = 1, CT_MAXSW = 2, CT_UPD = 3, CT_SWTOT = 4,
        CT_ROT = 8, CT_COUNT = 8 + MAXSW };
@@ -43,6 +44,24 @@ struct Slot {
   int n, chi, site_cap, m_cap;
   double tau, tie, tol_rel, tol_abs;
   int max_sweeps, pad;
+  double* prof;     // [PROF_N] constant-rate clock ticks per phase (WG 0)
+};
+
+// phase timers of workgroup 0 of each MPO
+enum { PF_THETA = 0, PF_GRAM, PF_CHECK, PF_EIGH, PF_ROTX, PF_ROTW, PF_WAIT,
+       PF_NORMS, PF_SELECT, PF_ABSORB, PF_MOVE_PREP, PF_MOVE_GEMM, PF_EIGH_SW,
+       PF_PAIRS, PF_WAIT_ALL, PF_N = 16 };
+
+struct PhaseClock {
+  bool on;
+  uint64_t t;
+  __device__ PhaseClock(bool active) : on(active), t(active ? wall_clock64() : 0) {}
+  __device__ void lap(double* prof, int slot) {
+    if (!on) return;
+    const uint64_t now = wall_clock64();
+    if (threadIdx.x == 0) prof[slot] += double(now - t);
+    t = now;
+  }
 };
 
 struct Step {
@@ -115,10 +134,14 @@ struct Group {
 };
 
 __device__ inline bool group_sync(Group& grp) {
-  __threadfence();
+  // every wave's global stores have completed before the workgroup barrier;
+  // thread 0 then publishes them device-wide (release), arrives, waits, and
+  // acquires (the vector L1 it invalidates is shared by the whole workgroup)
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   grp.nbar += 1;
   if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     atomicAdd(grp.bar, 1);
     const int target = grp.nbar * grp.G;
     int ok = 1;
@@ -134,10 +157,10 @@ __device__ inline bool group_sync(Group& grp) {
       }
       __builtin_amdgcn_s_sleep(1);
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *grp.sflag = ok;
   }
   __syncthreads();
-  __threadfence();
   const int ok = *grp.sflag;
   __syncthreads();
   return ok != 0;

@@ -81,6 +81,8 @@ __global__ void k_init(const Slot* slots, const double* init_sites, int n) {
   }
   for (int k = threadIdx.x; k <= n; k += blockDim.x) s.dims[k] = 1;
   for (int i = threadIdx.x; i < CT_COUNT; i += blockDim.x) s.ctr[i] = 0;
+  if (s.prof)
+    for (int i = threadIdx.x; i < PF_N; i += blockDim.x) s.prof[i] = 0.0;
   if (threadIdx.x == 0) {
     double lg = 0.0;
     for (int k = 0; k < n; ++k) {
@@ -94,6 +96,7 @@ __global__ void k_init(const Slot* slots, const double* init_sites, int n) {
     s.scal[SC_MINGAP] = 1.0;
     s.scal[SC_F2] = 0.0;
     s.scal[SC_KEPT] = 0.0;
+    s.scal[SC_FLOPS] = 0.0;
   }
 }
 
@@ -234,7 +237,7 @@ namespace {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t sites, X, W, Rm, norms, perm, sval, dims, scal, ctr, env, envlog, total;
+  size_t sites, X, W, Rm, norms, perm, sval, dims, scal, ctr, env, envlog, prof, total;
 };
 
 bool cfg_valid(const mpo_config* c) {
@@ -263,6 +266,7 @@ Layout layout_of(const mpo_config* c) {
   o.ctr = take(L * CT_COUNT * 4);
   o.env = take(L * 2 * (n + 1) * chi * 8);
   o.envlog = take(L * 2 * (n + 1) * 8);
+  o.prof = take(L * PF_N * 8);
   o.total = off;
   return o;
 }
@@ -374,7 +378,7 @@ void fill_defaults(mpo_config& c) {
   if (c.trunc_tol <= 0) c.trunc_tol = f64 ? 1e-14 : 1e-7;
   if (c.tie_tol <= 0) c.tie_tol = f64 ? 1e-10 : 1e-5;
   if (c.jacobi_tol <= 0) c.jacobi_tol = f64 ? 1e-13 : 2e-6;
-  if (c.max_sweeps <= 0) c.max_sweeps = f64 ? 20 : 14;
+  if (c.max_sweeps <= 0) c.max_sweeps = 30;
   if (c.block <= 0) c.block = BW;
 }
 
@@ -475,6 +479,7 @@ extern "C" int mpo_init(mpo_t** out, const mpo_config* cfg,
     s.tol_rel = c.jacobi_tol;
     s.tol_abs = c.precision == NZE_FP64 ? 1e-15 : 1e-6;
     s.max_sweeps = c.max_sweeps;
+    s.prof = reinterpret_cast<double*>(h->ws + lay.prof) + (size_t)l * PF_N;
     h->slots.push_back(s);
   }
   std::vector<double> init((size_t)4 * n);
@@ -690,6 +695,7 @@ extern "C" int mpo_stats(mpo_t* h, nze_stats* stats, int32_t* bonds) {
     s.max_sweeps = ct[CT_MAXSW];
     s.updates = ct[CT_UPD];
     s.sweeps_total = ct[CT_SWTOT];
+    s.flops = sc[SC_FLOPS];
     int mb = 0;
     for (int b = 1; b < n; ++b) {
       mb = std::max(mb, dims[(size_t)l * (n + 1) + b]);
@@ -698,6 +704,22 @@ extern "C" int mpo_stats(mpo_t* h, nze_stats* stats, int32_t* bonds) {
     s.max_bond = mb;
   }
   return read_errors(h);
+}
+
+extern "C" int mpo_profile(mpo_t* h, double* ms_out) {
+  if (!h || !ms_out) return fail(NZE_EINVAL, "bad arguments");
+  const int L = h->cfg.n_levels;
+  std::vector<double> t((size_t)L * PF_N);
+  HIPCHK(hipMemcpyAsync(t.data(), h->ws + h->lay.prof, t.size() * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  int dev, khz = 100000;
+  HIPCHK(hipGetDevice(&dev));
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+  for (size_t i = 0; i < t.size(); ++i) {
+    const int slot = (int)(i % PF_N);
+    ms_out[i] = (slot == PF_EIGH_SW || slot == PF_PAIRS) ? t[i] : t[i] / khz;
+  }
+  return NZE_OK;
 }
 
 extern "C" int mpo_bond_spectrum(mpo_t* h, int32_t lv, int32_t l, double* s_out,
@@ -831,7 +853,9 @@ extern "C" int nze_kernel_rowortho(int32_t precision, int32_t R, int32_t C,
   double* dscal = reinterpret_cast<double*>(scr);
   int* dctr = reinterpret_cast<int*>(scr + 256);
   int* dbar = reinterpret_cast<int*>(scr + 1024);
-  double* dnorm = reinterpret_cast<double*>(scr + 8192);
+  double* dnorm = reinterpret_cast<double*>(scr + 8192);               // R <= 2048 doubles
+  int* dperm = reinterpret_cast<int*>(scr + 8192 + 8 * 4 * CHI_LIMIT);   // R ints (row order)
+  static_assert(8192 + 12 * 4 * CHI_LIMIT <= HOOK_BYTES, "hook scratch too small");
   HIPCHK(hipMemsetAsync(scr, 0, 8192, st));
   Slot s;
   std::memset(&s, 0, sizeof(s));
@@ -840,6 +864,7 @@ extern "C" int nze_kernel_rowortho(int32_t precision, int32_t R, int32_t C,
   s.X = X;
   s.W = W;
   s.norms = dnorm;
+  s.perm = dperm;
   s.tol_rel = tol_rel;
   s.tol_abs = tol_abs;
   s.max_sweeps = max_sweeps;

@@ -181,6 +181,8 @@ __device__ void phase_theta(const Slot& s, int k, bool ltr, const double* R,
   }
   const double tot = block_sum(f2, red);
   if (tid == 0 && tot != 0.0) atomicAdd(&s.scal[SC_F2], tot);
+  if (g == 0 && tid == 0)   // contraction 2 (4cl) cm (4cr) + superoperator 512 cl cr
+    s.scal[SC_FLOPS] += 32.0 * cl * cm * cr + 512.0 * cl * cr;
   set_identity(reinterpret_cast<T*>(s.W), ltr ? 4 * cl : 4 * cr, g, G);
 }
 
@@ -222,18 +224,26 @@ __device__ void pair_gram(const T* X, int ld, int C, const PairLds& L) {
   const int i = lane & 15, kq = lane >> 4;
   const int r0 = L.rows[i], r1 = L.rows[16 + i];
   acc_t a00 = {0, 0, 0, 0}, a01 = {0, 0, 0, 0}, a11 = {0, 0, 0, 0};
-  for (int c0 = 16 * w; c0 < C; c0 += 64) {
-    const int c = c0 + 4 * kq;        // C is a multiple of 4
-    T x0[4] = {0, 0, 0, 0}, x1[4] = {0, 0, 0, 0};
-    if (c < C) {
-      if (r0 >= 0) load4(X + (size_t)r0 * ld + c, x0);
-      if (r1 >= 0) load4(X + (size_t)r1 * ld + c, x1);
+  // four 16-column chunks per iteration: all loads issued before the MFMAs
+  for (int c0 = 16 * w; c0 < C; c0 += 256) {
+    T x0[4][4], x1[4][4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int c = c0 + 64 * h + 4 * kq;   // C is a multiple of 4
+      for (int s = 0; s < 4; ++s) { x0[h][s] = T(0); x1[h][s] = T(0); }
+      if (c < C) {
+        if (r0 >= 0) load4(X + (size_t)r0 * ld + c, x0[h]);
+        if (r1 >= 0) load4(X + (size_t)r1 * ld + c, x1[h]);
+      }
     }
-    for (int s = 0; s < 4; ++s) {
-      a00 = mfma4(x0[s], x0[s], a00);
-      a01 = mfma4(x0[s], x1[s], a01);
-      a11 = mfma4(x1[s], x1[s], a11);
-    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        a00 = mfma4(x0[h][s], x0[h][s], a00);
+        a01 = mfma4(x0[h][s], x1[h][s], a01);
+        a11 = mfma4(x1[h][s], x1[h][s], a11);
+      }
   }
   double* P = L.Gp + w * 1024;
   for (int r = 0; r < 4; ++r) {
@@ -253,9 +263,54 @@ __device__ void pair_gram(const T* X, int ld, int C, const PairLds& L) {
   __syncthreads();
 }
 
-// Eigen-decomposition Gs = Qs diag Qs^T by cyclic parallel Jacobi (16
-// disjoint rotations per step, round-robin ordering), float64, in LDS.
-__device__ void inner_eigh(const PairLds& L) {
+// Reciprocal and reciprocal square root: hardware seeds (v_rcp_f64,
+// v_rsq_f64) refined by two Newton-Raphson steps, x_{k+1} = x_k (2 - a x_k)
+// and y_{k+1} = y_k (3 - a y_k^2) / 2; each step squares the relative error.
+__device__ inline double nr_rcp(double a) {
+  double x = __builtin_amdgcn_rcp(a);
+  x = x * fma(-a, x, 2.0);
+  x = x * fma(-a, x, 2.0);
+  return x;
+}
+__device__ inline double nr_rsq(double a) {
+  double y = __builtin_amdgcn_rsq(a);
+  y = y * fma(-0.5 * a * y, y, 1.5);
+  y = y * fma(-0.5 * a * y, y, 1.5);
+  return y;
+}
+
+// Jacobi rotation (c, s) that zeroes g_pq of the symmetric 2x2 block
+// [[g_pp, g_pq], [g_pq, g_qq]] (J = [[c, s], [-s, c]], J^T G J diagonal):
+// tau = (g_qq - g_pp) / (2 g_pq), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
+// c = 1 / sqrt(1 + t^2), s = t c.  Identity below the threshold.
+__device__ inline void jacobi_cs(double gpp, double gqq, double gpq,
+                                 double floor_abs, double& c, double& sn) {
+  c = 1.0;
+  sn = 0.0;
+  const double a2 = gpq * gpq;
+  if (fabs(gpq) > floor_abs && a2 > 1e-30 * fabs(gpp * gqq)) {
+    const double tau = (gqq - gpp) * nr_rcp(2.0 * gpq);
+    const double u = fma(tau, tau, 1.0);
+    const double t = (tau >= 0 ? 1.0 : -1.0) * nr_rcp(fabs(tau) + u * nr_rsq(u));
+    c = nr_rsq(fma(t, t, 1.0));
+    sn = t * c;
+  }
+}
+
+// Round-robin pairing of 32 indices: pair k (0..15) of step st.
+__device__ inline void rr_pair32(int k, int st, int& p, int& q) {
+  p = (k == 0) ? 0 : 1 + ((k - 1 + st) % 31);
+  q = 1 + ((30 - k + st) % 31);
+}
+
+// Cyclic parallel Jacobi on the 32x32 symmetric Gs (float64, LDS): up to
+// max_inner sweeps of 31 steps, 16 disjoint rotations per step; Qs
+// accumulates the rotations.  Every thread derives the two rotations it
+// needs from the current G, and G ping-pongs between Gs and a second buffer
+// (the dead Gram partials), so a step needs one barrier.  Thread t owns the
+// 2x2 block (pair t/16, pair t%16) of G and rows 2(t/16), 2(t/16)+1 of Qs
+// at pair t%16.  Returns the sweeps done; the final G is not kept.
+__device__ int inner_eigh(const PairLds& L, int max_inner) {
   const int tid = threadIdx.x;
   for (int e = tid; e < 32 * 32; e += NT) {
     const int u = e >> 5, v = e & 31;
@@ -264,58 +319,48 @@ __device__ void inner_eigh(const PairLds& L) {
   double dmax = 0.0;
   for (int u = 0; u < 32; ++u) dmax = fmax(dmax, L.Gs[u * GLD + u]);
   const double floor_abs = 1e-30 * dmax;
-  for (int sw = 0; sw < 40; ++sw) {
-    if (tid == 0) L.flag[0] = 0;
-    __syncthreads();
-    for (int step = 0; step < 31; ++step) {
-      if (tid < 16) {
-        const int p = (tid == 0) ? 0 : 1 + ((tid - 1 + step) % 31);
-        const int q = 1 + ((31 - tid - 1 + step) % 31);
-        const double gpp = L.Gs[p * GLD + p], gqq = L.Gs[q * GLD + q];
-        const double gpq = L.Gs[p * GLD + q];
-        double c = 1.0, sn = 0.0;
-        if (fabs(gpq) > floor_abs &&
-            fabs(gpq) > 1e-15 * sqrt(fabs(gpp) * fabs(gqq))) {
-          const double tau = (gqq - gpp) / (2.0 * gpq);
-          const double t = (tau >= 0 ? 1.0 : -1.0) /
-                           (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          sn = t * c;
-          L.flag[0] = 1;
-        }
-        L.cs[tid] = c;
-        L.sn[tid] = sn;
-        L.pp[tid] = p;
-        L.qq[tid] = q;
-      }
-      __syncthreads();
-      {
-        const int P = tid >> 4, P2 = tid & 15;
-        const int p = L.pp[P], q = L.qq[P], p2 = L.pp[P2], q2 = L.qq[P2];
-        const double c = L.cs[P], s = L.sn[P], c2 = L.cs[P2], s2 = L.sn[P2];
-        const double g11 = L.Gs[p * GLD + p2], g12 = L.Gs[p * GLD + q2];
-        const double g21 = L.Gs[q * GLD + p2], g22 = L.Gs[q * GLD + q2];
-        const double h11 = c * g11 - s * g21, h12 = c * g12 - s * g22;
-        const double h21 = s * g11 + c * g21, h22 = s * g12 + c * g22;
-        L.Gs[p * GLD + p2] = c2 * h11 - s2 * h12;
-        L.Gs[p * GLD + q2] = s2 * h11 + c2 * h12;
-        L.Gs[q * GLD + p2] = c2 * h21 - s2 * h22;
-        L.Gs[q * GLD + q2] = s2 * h21 + c2 * h22;
-      }
-      for (int e = tid; e < 512; e += NT) {
-        const int u = e >> 4, P = e & 15;
-        const int p = L.pp[P], q = L.qq[P];
-        const double c = L.cs[P], s = L.sn[P];
-        const double qp = L.Qs[u * GLD + p], qv = L.Qs[u * GLD + q];
-        L.Qs[u * GLD + p] = c * qp - s * qv;
-        L.Qs[u * GLD + q] = s * qp + c * qv;
-      }
+  const int P = tid >> 4, P2 = tid & 15;
+  double* Ga = L.Gs;
+  double* Gb = L.Gp;          // 32 x GLD, free once the Gram is reduced
+  __syncthreads();
+  for (int sw = 0; sw < max_inner; ++sw) {
+    int any = 0;
+    for (int st = 0; st < 31; ++st) {
+      int p, q, p2, q2;
+      rr_pair32(P, st, p, q);
+      rr_pair32(P2, st, p2, q2);
+      double c, sn, c2, s2;
+      jacobi_cs(Ga[p * GLD + p], Ga[q * GLD + q], Ga[p * GLD + q], floor_abs, c, sn);
+      if (P2 == P) { c2 = c; s2 = sn; }
+      else jacobi_cs(Ga[p2 * GLD + p2], Ga[q2 * GLD + q2], Ga[p2 * GLD + q2], floor_abs, c2, s2);
+      any |= (sn != 0.0);
+      const double g11 = Ga[p * GLD + p2], g12 = Ga[p * GLD + q2];
+      const double g21 = Ga[q * GLD + p2], g22 = Ga[q * GLD + q2];
+      const double h11 = c * g11 - sn * g21, h12 = c * g12 - sn * g22;
+      const double h21 = sn * g11 + c * g21, h22 = sn * g12 + c * g22;
+      Gb[p * GLD + p2] = c2 * h11 - s2 * h12;
+      Gb[p * GLD + q2] = s2 * h11 + c2 * h12;
+      Gb[q * GLD + p2] = c2 * h21 - s2 * h22;
+      Gb[q * GLD + q2] = s2 * h21 + c2 * h22;
+      const int u0 = 2 * P;
+      const double qa = L.Qs[u0 * GLD + p2], qb = L.Qs[u0 * GLD + q2];
+      const double qc = L.Qs[(u0 + 1) * GLD + p2], qd = L.Qs[(u0 + 1) * GLD + q2];
+      L.Qs[u0 * GLD + p2] = c2 * qa - s2 * qb;
+      L.Qs[u0 * GLD + q2] = s2 * qa + c2 * qb;
+      L.Qs[(u0 + 1) * GLD + p2] = c2 * qc - s2 * qd;
+      L.Qs[(u0 + 1) * GLD + q2] = s2 * qc + c2 * qd;
+      double* t = Ga; Ga = Gb; Gb = t;
       __syncthreads();
     }
+    if (tid == 0) L.flag[0] = 0;
+    __syncthreads();
+    if (any) L.flag[0] = 1;
+    __syncthreads();
     const int f = L.flag[0];
     __syncthreads();
-    if (!f) break;
+    if (!f) return sw + 1;
   }
+  return max_inner;
 }
 
 // rows <- Q^T rows for the pair's 32 rows of M (ld, ncols), in place.
@@ -331,21 +376,32 @@ __device__ void pair_rotate(T* M, int ld, int ncols, const PairLds& L) {
   for (int s = 0; s < 8; ++s) src[s] = L.rows[4 * s + kq];
   int dst0[4], dst1[4];
   for (int r = 0; r < 4; ++r) { dst0[r] = L.rows[mrow<T>(kq, r)]; dst1[r] = L.rows[16 + mrow<T>(kq, r)]; }
-  for (int c0 = 16 * w; c0 < ncols; c0 += 64) {
-    const int c = c0 + i;
-    const bool cok = c < ncols;
-    T xb[8];
-    for (int s = 0; s < 8; ++s)
-      xb[s] = (cok && src[s] >= 0) ? M[(size_t)src[s] * ld + c] : T(0);
-    acc_t d0 = {0, 0, 0, 0}, d1 = {0, 0, 0, 0};
-    for (int s = 0; s < 8; ++s) {
-      d0 = mfma4(qa[0][s], xb[s], d0);
-      d1 = mfma4(qa[1][s], xb[s], d1);
+  constexpr int NCH = 4;   // 16-column chunks in flight per wave
+  for (int c0 = 16 * w; c0 < ncols; c0 += 64 * NCH) {
+    T xb[NCH][8];
+#pragma unroll
+    for (int h = 0; h < NCH; ++h) {
+      const int c = c0 + 64 * h + i;
+      const bool cok = c < ncols;
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+        xb[h][s] = (cok && src[s] >= 0) ? M[(size_t)src[s] * ld + c] : T(0);
     }
-    if (cok) {
-      for (int r = 0; r < 4; ++r) {
-        if (dst0[r] >= 0) M[(size_t)dst0[r] * ld + c] = d0[r];
-        if (dst1[r] >= 0) M[(size_t)dst1[r] * ld + c] = d1[r];
+#pragma unroll
+    for (int h = 0; h < NCH; ++h) {
+      const int c = c0 + 64 * h + i;
+      acc_t d0 = {0, 0, 0, 0}, d1 = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        d0 = mfma4(qa[0][s], xb[h][s], d0);
+        d1 = mfma4(qa[1][s], xb[h][s], d1);
+      }
+      if (c < ncols) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (dst0[r] >= 0) M[(size_t)dst0[r] * ld + c] = d0[r];
+          if (dst1[r] >= 0) M[(size_t)dst1[r] * ld + c] = d1[r];
+        }
       }
     }
   }
@@ -354,26 +410,32 @@ __device__ void pair_rotate(T* M, int ld, int ncols, const PairLds& L) {
 // One pair step of sweep `sw`: Gram, convergence test, inner solve, rotate.
 template <typename T>
 __device__ void jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
-                            int J, int nb, int sw, double F2, double* smem) {
+                            int J, int nb, int sw, double F2, double* smem,
+                            bool timed, const int* order) {
   const PairLds L = pair_lds(smem);
   const int tid = threadIdx.x;
+  PhaseClock clk(timed && s.prof != nullptr);
   __syncthreads();
   if (tid < 32) {
     const int blk = tid < 16 ? I : J;
     const int r = blk * BW + (tid & 15);
-    L.rows[tid] = (blk < nb && r < R) ? r : -1;
+    L.rows[tid] = (blk < nb && r < R) ? order[r] : -1;
   }
   if (tid == 0) L.flag[1] = 0;
   __syncthreads();
   pair_gram<T>(X, C, C, L);
-  // convergence test: |g_uv| > tol_rel sqrt(g_uu g_vv) + tol_abs sqrt(F2 max)
+  clk.lap(s.prof, PF_GRAM);
+  // convergence test: |g_uv| > tol sqrt(g_uu g_vv) + tol_abs sqrt(F2 max);
+  // tol is raised to the rounding level of a length-C dot product
+  const double eps = sizeof(T) == 4 ? 5.96e-8 : 1.11e-16;
+  const double tol = fmax(s.tol_rel, 8.0 * sqrt((double)C) * eps);
   int need = 0;
   for (int e = tid; e < 1024; e += NT) {
     const int u = e >> 5, v = e & 31;
     if (v <= u) continue;
     const double guu = L.Gs[u * GLD + u], gvv = L.Gs[v * GLD + v];
     const double guv = fabs(L.Gs[u * GLD + v]);
-    if (!(guv <= s.tol_rel * sqrt(guu * gvv) +
+    if (!(guv <= tol * sqrt(guu * gvv) +
                      s.tol_abs * sqrt(F2 * fmax(guu, gvv))))
       need = 1;
   }
@@ -381,12 +443,61 @@ __device__ void jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
   __syncthreads();
   const int go = L.flag[1];
   __syncthreads();
+  clk.lap(s.prof, PF_CHECK);
   if (!go) return;
   if (tid == 0) atomicAdd(&s.ctr[CT_ROT + sw], 1);
-  inner_eigh(L);
+  const int nsw = inner_eigh(L, INNER_SWEEPS);
+  clk.lap(s.prof, PF_EIGH);
+  if (clk.on && tid == 0) { s.prof[PF_EIGH_SW] += nsw; s.prof[PF_PAIRS] += 1.0; }
   pair_rotate<T>(X, C, C, L);
+  clk.lap(s.prof, PF_ROTX);
   pair_rotate<T>(W, R, R, L);
   __syncthreads();
+  clk.lap(s.prof, PF_ROTW);
+}
+
+// squared row norms in float64
+template <typename T>
+__device__ void phase_norms(const Slot& s, const T* X, int R, int C, int g,
+                            int G) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int r = g * 4 + w; r < R; r += 4 * G) {
+    double acc = 0.0;
+    const T* x = X + (size_t)r * C;
+    for (int c = lane; c < C; c += 64) acc += double(x[c]) * double(x[c]);
+    acc = wave_sum(acc);
+    if (lane == 0) s.norms[r] = acc;
+  }
+}
+
+// One workgroup: s.perm[0..R) = rows ordered by decreasing squared norm
+// (ties by index).  Bitonic sort of (key, index) pairs in LDS.
+__device__ void sort_rows(const Slot& s, int R, double* key, int* idx) {
+  int N = 1;
+  while (N < R) N <<= 1;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) {
+    key[i] = i < R ? s.norms[i] : -1.0;
+    idx[i] = i;
+  }
+  __syncthreads();
+  for (int size = 2; size <= N; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = tid; i < N; i += NT) {
+        const int j = i ^ stride;
+        if (j > i) {
+          const bool desc = (i & size) == 0;
+          const double ki = key[i], kj = key[j];
+          const int ii = idx[i], ij = idx[j];
+          const bool i_first = ki > kj || (ki == kj && ii < ij);
+          if (desc ? !i_first : i_first) {
+            key[i] = kj; key[j] = ki; idx[i] = ij; idx[j] = ii;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
 }
 
 // Round-robin tournament: block at position `pos` in round t (nbe even).
@@ -405,13 +516,31 @@ __device__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, int C, int g,
   int sweeps = 0;
   bool conv = false;
   for (int sw = 0; sw < s.max_sweeps && sw < MAXSW; ++sw) {
+    // blocks are consecutive runs of the rows sorted by decreasing norm
+    phase_norms<T>(s, X, R, C, g, G);
+    if (!group_sync(grp)) return false;
+    if (g == 0) {
+      double* key = smem;
+      int* idx = reinterpret_cast<int*>(smem + 4 * CHI_LIMIT);
+      sort_rows(s, R, key, idx);
+      for (int i = threadIdx.x; i < R; i += NT) s.perm[i] = idx[i];
+    }
+    if (!group_sync(grp)) return false;
     for (int t = 0; t < rounds; ++t) {
       for (int q = g; q < npair; q += G) {
         const int I = tourney_block(q, t, nbe);
         const int J = tourney_block(nbe - 1 - q, t, nbe);
-        jacobi_pair<T>(s, X, W, R, C, I, J, nb, sw, F2, smem);
+        jacobi_pair<T>(s, X, W, R, C, I, J, nb, sw, F2, smem, g == 0, s.perm);
       }
+      PhaseClock wclk(s.prof != nullptr);
       if (!group_sync(grp)) return false;
+      if (wclk.on) {
+        const uint64_t now = wall_clock64();
+        if (threadIdx.x == 0) {
+          if (g == 0) s.prof[PF_WAIT] += double(now - wclk.t);
+          atomicAdd(&s.prof[PF_WAIT_ALL], double(now - wclk.t) / G);
+        }
+      }
     }
     sweeps = sw + 1;
     const int rot = __hip_atomic_load(&s.ctr[CT_ROT + sw], __ATOMIC_RELAXED,
@@ -419,25 +548,12 @@ __device__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, int C, int g,
     if (rot == 0) { conv = true; break; }
   }
   if (g == 0 && threadIdx.x == 0) {
+    s.scal[SC_FLOPS] += 4.0 * sweeps * double(R) * double(R) * (2.0 * C + R);
     s.ctr[CT_SWTOT] += sweeps;
     if (sweeps > s.ctr[CT_MAXSW]) s.ctr[CT_MAXSW] = sweeps;
     if (!conv) s.ctr[CT_ERR] |= ERR_NOCONV;
   }
   return true;
-}
-
-// squared row norms in float64
-template <typename T>
-__device__ void phase_norms(const Slot& s, const T* X, int R, int C, int g,
-                            int G) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int r = g * 4 + w; r < R; r += 4 * G) {
-    double acc = 0.0;
-    const T* x = X + (size_t)r * C;
-    for (int c = lane; c < C; c += 64) acc += double(x[c]) * double(x[c]);
-    acc = wave_sum(acc);
-    if (lane == 0) s.norms[r] = acc;
-  }
 }
 
 // One workgroup: sort the squared norms, pick the rank, update fidelity and
@@ -451,29 +567,7 @@ __device__ void phase_select(const Slot& s, int R, bool gate, double* smem) {
   double* red = smem + N + (N + 1) / 2 + 2;
   int* sh = reinterpret_cast<int*>(red + 8);
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += NT) {
-    key[i] = i < R ? s.norms[i] : -1.0;
-    idx[i] = i;
-  }
-  __syncthreads();
-  // bitonic sort, decreasing key, ties by increasing index
-  for (int size = 2; size <= N; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = tid; i < N; i += NT) {
-        const int j = i ^ stride;
-        if (j > i) {
-          const bool desc = (i & size) == 0;
-          const double ki = key[i], kj = key[j];
-          const int ii = idx[i], ij = idx[j];
-          const bool i_first = ki > kj || (ki == kj && ii < ij);
-          if (desc ? !i_first : i_first) {
-            key[i] = kj; key[j] = ki; idx[i] = ij; idx[j] = ii;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
+  sort_rows(s, R, key, idx);
   double tot = 0.0;
   for (int i = tid; i < R; i += NT) tot += fmax(key[i], 0.0);
   tot = block_sum(tot, red);
@@ -539,13 +633,18 @@ __device__ bool op_gate(const Slot& s, int k, bool ltr, const double* R, int g,
   const int Rr = ltr ? 4 * cl : 4 * cr, Cc = ltr ? 4 * cr : 4 * cl;
   T* X = reinterpret_cast<T*>(s.X);
   T* W = reinterpret_cast<T*>(s.W);
+  PhaseClock clk(g == 0 && s.prof != nullptr);
   phase_theta<T>(s, k, ltr, R, g, G, smem);
   if (!group_sync(grp)) return false;
+  clk.lap(s.prof, PF_THETA);
   if (!phase_jacobi<T>(s, X, W, Rr, Cc, g, G, grp, smem)) return false;
+  clk.lap(s.prof, 15);
   phase_norms<T>(s, X, Rr, Cc, g, G);
   if (!group_sync(grp)) return false;
+  clk.lap(s.prof, PF_NORMS);
   if (g == 0) phase_select(s, Rr, true, smem);
   if (!group_sync(grp)) return false;
+  clk.lap(s.prof, PF_SELECT);
   const int r = s.ctr[CT_RANK];
   const double inv = 1.0 / sqrt(s.scal[SC_KEPT]);
   T* Mk = site_ptr<T>(s, k);
@@ -559,7 +658,9 @@ __device__ bool op_gate(const Slot& s, int k, bool ltr, const double* R, int g,
   }
   if (!group_sync(grp)) return false;
   if (g == 0 && threadIdx.x == 0) s.dims[k + 1] = r;
-  return group_sync(grp);
+  const bool ok = group_sync(grp);
+  clk.lap(s.prof, PF_ABSORB);
+  return ok;
 }
 
 // Centre move away from site c: to c+1 (ltr) or c-1.
@@ -572,6 +673,7 @@ __device__ bool op_move(const Slot& s, int c, bool ltr, int g, int G,
   T* Rm = reinterpret_cast<T*>(s.Rm);
   T* M = site_ptr<T>(s, c);
   const int Rr = ltr ? cr : cl, Cc = ltr ? 4 * cl : 4 * cr;
+  PhaseClock clk(g == 0 && s.prof != nullptr);
   // X = M^T (chi_r x 4 chi_l) or M (chi_l x 4 chi_r); F2
   {
     double f2 = 0.0;
@@ -612,11 +714,14 @@ __device__ bool op_move(const Slot& s, int c, bool ltr, int g, int G,
     set_identity(W, Rr, g, G);
   }
   if (!group_sync(grp)) return false;
+  clk.lap(s.prof, PF_MOVE_PREP);
   if (!phase_jacobi<T>(s, X, W, Rr, Cc, g, G, grp, smem)) return false;
+  clk.lap(s.prof, 15);
   phase_norms<T>(s, X, Rr, Cc, g, G);
   if (!group_sync(grp)) return false;
   if (g == 0) phase_select(s, Rr, false, smem);
   if (!group_sync(grp)) return false;
+  clk.lap(s.prof, PF_SELECT);
   const int r = s.ctr[CT_RANK];
   if (ltr) {
     // M_c = Y^T S^-1 (4cl x r);  Rm = S W_perm (r x cr)
@@ -632,6 +737,7 @@ __device__ bool op_move(const Slot& s, int c, bool ltr, int g, int G,
     const int c2 = s.dims[c + 2];
     T* Mn = site_ptr<T>(s, c + 1);          // cr x 4c2
     gemm_nn<T>(Rm, cr, Mn, 4 * c2, X, 4 * c2, r, 4 * c2, cr, g, G);
+    if (g == 0 && threadIdx.x == 0) s.scal[SC_FLOPS] += 8.0 * r * cr * c2;
     if (!group_sync(grp)) return false;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int i = g * 4 + w; i < r; i += 4 * G)
@@ -643,6 +749,7 @@ __device__ bool op_move(const Slot& s, int c, bool ltr, int g, int G,
     const int c0 = s.dims[c - 1];
     T* Mp = site_ptr<T>(s, c - 1);          // 4c0 x cl
     gemm_nn<T>(Mp, cl, Rm, r, X, r, 4 * c0, r, cl, g, G);
+    if (g == 0 && threadIdx.x == 0) s.scal[SC_FLOPS] += 8.0 * c0 * cl * r;
     if (!group_sync(grp)) return false;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int i = g * 4 + w; i < 4 * c0; i += 4 * G)
@@ -651,7 +758,9 @@ __device__ bool op_move(const Slot& s, int c, bool ltr, int g, int G,
     if (!group_sync(grp)) return false;
     if (g == 0 && threadIdx.x == 0) s.dims[c] = r;
   }
-  return group_sync(grp);
+  const bool ok = group_sync(grp);
+  clk.lap(s.prof, PF_MOVE_GEMM);
+  return ok;
 }
 
 }  // namespace nze

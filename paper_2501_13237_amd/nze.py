@@ -40,7 +40,8 @@ class NzeStats(ctypes.Structure):
                 ("max_discarded", ctypes.c_double),
                 ("min_cut_gap", ctypes.c_double),
                 ("max_bond", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
-                ("updates", ctypes.c_int64), ("sweeps_total", ctypes.c_int64)]
+                ("updates", ctypes.c_int64), ("sweeps_total", ctypes.c_int64),
+                ("flops", ctypes.c_double)]
 
 
 class NzeFitOpts(ctypes.Structure):
@@ -91,6 +92,7 @@ def lib():
                                     ctypes.c_int32, c_double_p, ctypes.c_int32,
                                     c_int32_p]
     L.mpo_sync.argtypes = [ctypes.c_void_p]
+    L.mpo_profile.argtypes = [ctypes.c_void_p, c_double_p]
     L.nze_kernel_theta.argtypes = [ctypes.c_int32] * 4 + [
         ctypes.c_void_p, ctypes.c_void_p, c_double_p, ctypes.c_int32,
         ctypes.c_void_p, ctypes.c_void_p]
@@ -304,7 +306,18 @@ class MPO:
                      max_discarded=s.max_discarded,
                      min_cut_gap=s.min_cut_gap, max_bond=s.max_bond,
                      max_sweeps=s.max_sweeps, updates=s.updates,
-                     sweeps_total=s.sweeps_total) for s in st], bonds
+                     sweeps_total=s.sweeps_total, flops=s.flops)
+                for s in st], bonds
+
+    PROFILE_NAMES = ["theta", "gram", "check", "eigh", "rot_x", "rot_w",
+                     "jacobi_wait", "norms", "select", "absorb", "move_prep",
+                     "move_absorb", "inner_sweeps", "pair_solves", "wait_mean",
+                     "jacobi_total"]
+
+    def profile(self):
+        out = np.zeros((self.levels, 16))
+        _check(lib().mpo_profile(self.h, _dp(out)))
+        return [dict(zip(self.PROFILE_NAMES, row)) for row in out]
 
     def sync(self):
         _check(lib().mpo_sync(self.h))
