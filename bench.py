@@ -68,6 +68,15 @@ def run_job(nze, w, layers, precision, return_mpo=False):
     return out
 
 
+def saturated_rate(layers, layer_ms, levels, first=6):
+    """Updates/s over the layers whose bonds are all saturated (every layer
+    from the seventh on at chi = 256, n = 50), from the per-layer events."""
+    upd = sum(len(ls) for ls, _ in layers[first:]) * levels
+    ms = sum(layer_ms[first:])
+    return {"from_layer": first + 1, "updates": upd, "kernel_ms": ms,
+            "updates_per_s": 1e3 * upd / ms if ms > 0 else None}
+
+
 def cpu_baseline(w, layers, timed_layer=5, budget_s=40.0):
     """The oracle on noise level 1: evolve the first layers (bonds grow to
     chi), then time one layer whose bonds are saturated."""
@@ -92,6 +101,69 @@ def cpu_baseline(w, layers, timed_layer=5, budget_s=40.0):
                        f"{dt:.2f} s, bonds up to {max(m.bond_dims())})")}
 
 
+def serve_jobs(count, seed, workloads, nze):
+    """Synthetic job stream: n ~ U{16..64}, depth ~ U{10..30},
+    chi ~ U{64, 128, 256}, 4-8 levels evenly spaced in [1, 16] x 1e-3
+    (two-qubit depolarizing), Haar brickwork seeded per job, observables
+    <Z_(n/2)> and <X_1 X_2>.  Inputs (PTMs) are prepared before the clock."""
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for i in range(count):
+        n = int(rng.integers(16, 65))
+        depth = int(rng.integers(10, 31))
+        chi = int(rng.choice([64, 128, 256]))
+        L = int(rng.integers(4, 9))
+        factors = list(np.linspace(1.0, 16.0, L))
+        layers = workloads.brickwork(n, depth, seed=10000 * seed + i)
+        ptms = [nze.layer_ptms(us, {"dep": 1e-3}, factors) for _, us in layers]
+        obs = [workloads.pauli_string(n, {n // 2: "Z"}),
+               workloads.pauli_string(n, {1: "X", 2: "X"})]
+        upd = workloads.n_gates(layers) * L
+        jobs.append(dict(n=n, depth=depth, chi=chi, L=L, layers=[ls for ls, _ in layers],
+                         ptms=ptms, obs=obs, updates=upd))
+    return jobs
+
+
+def serve_run(nze, jobs, rate, seed, precision):
+    """Poisson arrivals at `rate` jobs/s into the serving loop; latency is
+    arrival -> result available on the host."""
+    rng = np.random.default_rng(seed + 7)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(jobs)))
+    srv = nze.Server(64 << 30, max_active=64)
+    t0 = time.perf_counter()
+    ids, lat, done_upd = {}, {}, 0
+    nxt = 0
+    while len(lat) < len(jobs):
+        now = time.perf_counter() - t0
+        while nxt < len(jobs) and arrivals[nxt] <= now:
+            j = jobs[nxt]
+            ids[srv.submit(j["n"], j["chi"], precision, j["layers"], j["ptms"],
+                           j["obs"])] = nxt
+            nxt += 1
+        a, q, d = srv.step()
+        if a == 0 and q == 0 and nxt < len(jobs):
+            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+        for jid, k in ids.items():
+            if k in lat:
+                continue
+            st, vals, fid, _ = srv.poll(jid)
+            if st == 2:
+                lat[k] = (time.perf_counter() - t0) - arrivals[k]
+                done_upd += jobs[k]["updates"]
+            elif st < 0:
+                raise RuntimeError(f"job {k} failed with {st}")
+    wall = time.perf_counter() - t0
+    hw, launches = srv.stats()
+    srv.close()
+    la = np.array([lat[k] for k in range(len(jobs))])
+    return {"offered_rate_jobs_per_s": rate, "jobs": len(jobs),
+            "p50_latency_s": float(np.percentile(la, 50)),
+            "p99_latency_s": float(np.percentile(la, 99)),
+            "completed_jobs_per_s": len(jobs) / wall,
+            "updates_per_s": done_upd / wall, "wall_s": wall,
+            "launches": int(launches), "arena_high_water_gib": hw / 2 ** 30}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +173,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--depth", type=int, default=None,
                     help="override the depth (diagnostics only)")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="also run the serving loop on this many jobs")
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-sustainable-rate", type=float, default=0.0)
+    ap.add_argument("--skip-main", action="store_true",
+                    help="only the serving runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus must be 1 "
@@ -117,6 +195,17 @@ def main():
         w.depth = args.depth
     layers = w.circuit()
     upd_per_job = workloads.n_gates(layers) * len(w.factors)
+
+    if args.skip_main:
+        out = {"metric": "p50/p99 job latency (serving)", "unit": "s",
+               "n_gpus": 1, "data": "synthetic"}
+        jobs = serve_jobs(args.serve, 1, workloads, nze)
+        out["serving"] = serve_run(nze, jobs, args.serve_rate, 1, nze.NZE_MIXED)
+        if args.serve_sustainable_rate > 0:
+            out["serving_sustainable"] = serve_run(
+                nze, jobs, args.serve_sustainable_rate, 1, nze.NZE_MIXED)
+        print(json.dumps(out), flush=True)
+        return
 
     def timed(precision, steps, warmup):
         for _ in range(warmup):
@@ -162,6 +251,7 @@ def main():
                      "kernel": "k_layer (persistent, one launch per layer)",
                      "mean_layer_ms": float(np.mean(layer_ms)),
                      "algorithmic_tflop_per_step": flops_job / 1e12},
+        "saturated_layers": saturated_rate(layers, layer_ms, len(w.factors)),
         "fidelity": [float(x) for x in fid],
         "jacobi_sweeps_total": int(sum(s["sweeps_total"] for s in stats)),
         "extrapolation": {str(k): v for k, v in fits.items()},

@@ -99,8 +99,10 @@ typedef struct mpo_config {
   double jacobi_tol;   /* relative off-diagonal threshold of the one-sided
                           Jacobi SVD: rows u, v count as orthogonal when
                           |<x_u,x_v>| <= tol |x_u||x_v| + tol_abs |X| |x_max|;
-                          tol is raised to at least 8 sqrt(C) eps of the path
-                          (C = row length); 0 -> 1e-13 (FP64) / 2e-6 (mixed);
+                          tol is raised to at least 8 sqrt(min(C, 64)) eps of
+                          the path (C = row length; the block Grams sum MFMA
+                          partials over 64 columns in float64);
+                          0 -> 1e-13 (FP64) / 2e-6 (mixed);
                           tol_abs is 1e-15 (FP64) / 1e-6 (mixed)             */
   int32_t max_sweeps;  /* Jacobi sweep cap (<= 40); 0 -> 30                   */
   int32_t block;       /* Jacobi row-block width b (pairs are 2b rows);
@@ -254,6 +256,50 @@ int nze_extrapolate(int32_t n_pts, const double* lambda, const double* value,
 int nze_fidelity_extrapolate(int32_t n_pts, const double* value,
                              const double* fidelity, double* out_value,
                              int32_t* converged);
+
+/* --------------------------------------------------------------- serving */
+/* A request loop over many extrapolation jobs (continuous batching).  Jobs
+ * are admitted in arrival order when their mpo_footprint fits into free
+ * space of a caller-owned device arena and a slot is free; admitted jobs stay
+ * resident, and every nze_server_step advances all resident jobs by one layer
+ * in shared persistent launches (at most 128 MPOs per launch).  A job that has
+ * run all its layers is read out (mpo_expect) and its memory is released.
+ * Because every MPO is computed by its own workgroups with the same
+ * arithmetic, a job's results do not depend on which jobs share its launches.
+ * The server is single-threaded; all work runs on `stream`. */
+typedef struct nze_server nze_server_t;
+
+typedef struct nze_job_spec {
+  int32_t n, chi_max, n_levels, precision;  /* as in mpo_config               */
+  int32_t n_layers;
+  const int32_t* layer_gates;   /* [n_layers] gates in each layer              */
+  const int32_t* left_sites;    /* the layers' left sites, concatenated (each
+                                   layer as in mpo_apply_layer)               */
+  const double* ptm;            /* the layers' PTMs, concatenated, each layer
+                                   [n_levels][gates][16][16] float64         */
+  int32_t n_obs;
+  const uint8_t* paulis;        /* [n_obs][n] Pauli codes                     */
+} nze_job_spec;
+
+/* arena: 256-byte aligned device memory of arena_bytes, caller-owned.
+ * max_active: most jobs resident at once. */
+int nze_server_create(nze_server_t** out, void* arena, size_t arena_bytes,
+                      int32_t max_active, void* stream);
+void nze_server_free(nze_server_t* s);
+/* Copies the job (host arrays); *job_id identifies it.  NZE_ENOMEM when the
+ * job could never fit the arena. */
+int nze_server_submit(nze_server_t* s, const nze_job_spec* spec, int64_t* job_id);
+/* Admission, one batched layer for every resident job, read-out of finished
+ * jobs.  Outputs (may be NULL): resident jobs, queued jobs, finished jobs. */
+int nze_server_step(nze_server_t* s, int32_t* n_active, int32_t* n_queued,
+                    int32_t* n_done);
+/* state: 0 queued, 1 resident, 2 done, < 0 error code.  When done, values
+ * [n_levels][n_obs] and fidelity [n_levels] are filled (NULL ok).  times[3]
+ * (NULL ok): submit, admission and completion, seconds on the server clock. */
+int nze_server_poll(nze_server_t* s, int64_t job_id, int32_t* state,
+                    double* values, double* fidelity, double* times);
+/* Highest arena offset in use so far (bytes) and launches issued. */
+int nze_server_stats(nze_server_t* s, size_t* arena_high_water, int64_t* launches);
 
 /* ------------------------------------------------------- kernel-level hooks */
 /* Single kernels of the update on caller buffers, for kernel-level parity

@@ -7,7 +7,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnze.so")
 
-SOURCES = ["nze_mpo.hip", "nze_host.cpp"]
+SOURCES = ["nze_mpo.hip", "nze_host.cpp", "nze_serve.cpp"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          # no packed fp32 instructions on this target
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

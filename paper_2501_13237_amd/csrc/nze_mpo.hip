@@ -751,16 +751,7 @@ __global__ __launch_bounds__(NT) void k_rowortho(Slot s, int R, int C, int G,
   const int g = blockIdx.x;
   T* X = reinterpret_cast<T*>(s.X);
   T* W = reinterpret_cast<T*>(s.W);
-  // F2 = ||X||^2 and W = I
-  {
-    double f2 = 0.0;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int r = g * 4 + w; r < R; r += 4 * G)
-      for (int c = lane; c < C; c += 64) f2 += double(X[(size_t)r * C + c]) * double(X[(size_t)r * C + c]);
-    const double tot = block_sum(f2, smem);
-    if (threadIdx.x == 0 && tot != 0.0) atomicAdd(&s.scal[SC_F2], tot);
-    set_identity(W, R, g, G);
-  }
+  set_identity(W, R, g, G);
   if (!group_sync(grp)) { if (g == 0 && threadIdx.x == 0) atomicOr(&s.ctr[CT_ERR], ERR_ABORT); return; }
   if (!phase_jacobi<T>(s, X, W, R, C, g, G, grp, smem)) { if (g == 0 && threadIdx.x == 0) atomicOr(&s.ctr[CT_ERR], ERR_ABORT); return; }
   phase_norms<T>(s, X, R, C, g, G);

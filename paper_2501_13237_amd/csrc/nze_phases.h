@@ -133,13 +133,11 @@ __device__ void phase_theta(const Slot& s, int k, bool ltr, const double* R,
   const int ldx = ltr ? 4 * cr : 4 * cl;
   T* tile = reinterpret_cast<T*>(smem);                          // [64][65]
   double* Rs = smem + (64 * 65 * sizeof(T) + 7) / 8;              // [256]
-  double* red = Rs + 256;                                         // [4]
   const int tid = threadIdx.x;
   Rs[tid] = R[tid];
   const int lane = tid & 63, w = tid >> 6;
   const int i = lane & 15, kq = lane >> 4;
   const int ta = (cl + 15) / 16, tb = (cr + 15) / 16;
-  double f2 = 0.0;
   for (int t = g; t < ta * tb; t += G) {
     const int a0 = (t / tb) * 16, b0 = (t % tb) * 16;
     const int row = a0 * 4 + 16 * w + i;
@@ -173,14 +171,11 @@ __device__ void phase_theta(const Slot& s, int k, bool ltr, const double* R,
           const int P = 4 * p2 + q2;
           T o = T(0);
           for (int Q = 0; Q < 16; ++Q) o += T(Rs[P * 16 + Q]) * th[Q];
-          f2 += double(o) * double(o);
           if (ltr) X[(size_t)(a * 4 + p2) * ldx + q2 * cr + b] = o;
           else X[(size_t)(q2 * cr + b) * ldx + a * 4 + p2] = o;
         }
     }
   }
-  const double tot = block_sum(f2, red);
-  if (tid == 0 && tot != 0.0) atomicAdd(&s.scal[SC_F2], tot);
   if (g == 0 && tid == 0)   // contraction 2 (4cl) cm (4cr) + superoperator 512 cl cr
     s.scal[SC_FLOPS] += 32.0 * cl * cm * cr + 512.0 * cl * cr;
   set_identity(reinterpret_cast<T*>(s.W), ltr ? 4 * cl : 4 * cr, g, G);
@@ -223,8 +218,8 @@ __device__ void pair_gram(const T* X, int ld, int C, const PairLds& L) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
   const int r0 = L.rows[i], r1 = L.rows[16 + i];
-  acc_t a00 = {0, 0, 0, 0}, a01 = {0, 0, 0, 0}, a11 = {0, 0, 0, 0};
-  // four 16-column chunks per iteration: all loads issued before the MFMAs
+  // MFMA partial sums over 64 columns, accumulated in float64 across chunks
+  double g00[4] = {0, 0, 0, 0}, g01[4] = {0, 0, 0, 0}, g11[4] = {0, 0, 0, 0};
   for (int c0 = 16 * w; c0 < C; c0 += 256) {
     T x0[4][4], x1[4][4];
 #pragma unroll
@@ -236,6 +231,7 @@ __device__ void pair_gram(const T* X, int ld, int C, const PairLds& L) {
         if (r1 >= 0) load4(X + (size_t)r1 * ld + c, x1[h]);
       }
     }
+    acc_t a00 = {0, 0, 0, 0}, a01 = {0, 0, 0, 0}, a11 = {0, 0, 0, 0};
 #pragma unroll
     for (int h = 0; h < 4; ++h)
 #pragma unroll
@@ -244,13 +240,18 @@ __device__ void pair_gram(const T* X, int ld, int C, const PairLds& L) {
         a01 = mfma4(x0[h][s], x1[h][s], a01);
         a11 = mfma4(x1[h][s], x1[h][s], a11);
       }
+    for (int r = 0; r < 4; ++r) {
+      g00[r] += double(a00[r]);
+      g01[r] += double(a01[r]);
+      g11[r] += double(a11[r]);
+    }
   }
   double* P = L.Gp + w * 1024;
   for (int r = 0; r < 4; ++r) {
     const int u = mrow<T>(kq, r);
-    P[u * 32 + i] = a00[r];
-    P[u * 32 + 16 + i] = a01[r];
-    P[(16 + u) * 32 + 16 + i] = a11[r];
+    P[u * 32 + i] = g00[r];
+    P[u * 32 + 16 + i] = g01[r];
+    P[(16 + u) * 32 + 16 + i] = g11[r];
   }
   __syncthreads();
   for (int e = threadIdx.x; e < 1024; e += NT) {
@@ -426,9 +427,10 @@ __device__ void jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
   pair_gram<T>(X, C, C, L);
   clk.lap(s.prof, PF_GRAM);
   // convergence test: |g_uv| > tol sqrt(g_uu g_vv) + tol_abs sqrt(F2 max);
-  // tol is raised to the rounding level of a length-C dot product
+  // tol is raised to the rounding level of the block Gram (MFMA partial sums
+  // over at most 64 columns, accumulated in float64)
   const double eps = sizeof(T) == 4 ? 5.96e-8 : 1.11e-16;
-  const double tol = fmax(s.tol_rel, 8.0 * sqrt((double)C) * eps);
+  const double tol = fmax(s.tol_rel, 8.0 * sqrt((double)(C < 64 ? C : 64)) * eps);
   int need = 0;
   for (int e = tid; e < 1024; e += NT) {
     const int u = e >> 5, v = e & 31;
@@ -511,8 +513,6 @@ __device__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, int C, int g,
   const int nb = (R + BW - 1) / BW;
   const int nbe = nb + (nb & 1);
   const int rounds = nbe - 1, npair = nbe / 2;
-  const double F2 = __hip_atomic_load(&s.scal[SC_F2], __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
   int sweeps = 0;
   bool conv = false;
   for (int sw = 0; sw < s.max_sweeps && sw < MAXSW; ++sw) {
@@ -522,10 +522,17 @@ __device__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, int C, int g,
     if (g == 0) {
       double* key = smem;
       int* idx = reinterpret_cast<int*>(smem + 4 * CHI_LIMIT);
+      // ||X||_F^2 in a fixed summation order (the absolute convergence floor)
+      double f2 = 0.0;
+      for (int i = threadIdx.x; i < R; i += NT) f2 += s.norms[i];
+      f2 = block_sum(f2, smem + 6 * CHI_LIMIT);
       sort_rows(s, R, key, idx);
       for (int i = threadIdx.x; i < R; i += NT) s.perm[i] = idx[i];
+      if (threadIdx.x == 0) s.scal[SC_F2] = f2;
     }
     if (!group_sync(grp)) return false;
+    const double F2 = __hip_atomic_load(&s.scal[SC_F2], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
     for (int t = 0; t < rounds; ++t) {
       for (int q = g; q < npair; q += G) {
         const int I = tourney_block(q, t, nbe);
@@ -674,9 +681,8 @@ __device__ bool op_move(const Slot& s, int c, bool ltr, int g, int G,
   T* M = site_ptr<T>(s, c);
   const int Rr = ltr ? cr : cl, Cc = ltr ? 4 * cl : 4 * cr;
   PhaseClock clk(g == 0 && s.prof != nullptr);
-  // X = M^T (chi_r x 4 chi_l) or M (chi_l x 4 chi_r); F2
+  // X = M^T (chi_r x 4 chi_l) or M (chi_l x 4 chi_r)
   {
-    double f2 = 0.0;
     if (ltr) {
       T* tile = reinterpret_cast<T*>(smem);
       const int na = 4 * cl;   // rows of M
@@ -689,7 +695,6 @@ __device__ bool op_move(const Slot& s, int c, bool ltr, int g, int G,
           T v = T(0);
           if (a0 + al < na && j0 + jl < cr) v = M[(size_t)(a0 + al) * cr + j0 + jl];
           tile[al * 33 + jl] = v;
-          f2 += double(v) * double(v);
         }
         __syncthreads();
         for (int e = threadIdx.x; e < 1024; e += NT) {
@@ -705,12 +710,8 @@ __device__ bool op_move(const Slot& s, int c, bool ltr, int g, int G,
         for (int cc = lane; cc < Cc; cc += 64) {
           const T v = M[(size_t)r * Cc + cc];
           X[(size_t)r * Cc + cc] = v;
-          f2 += double(v) * double(v);
         }
     }
-    double* red = smem + 2048;
-    const double tot = block_sum(f2, red);
-    if (threadIdx.x == 0 && tot != 0.0) atomicAdd(&s.scal[SC_F2], tot);
     set_identity(W, Rr, g, G);
   }
   if (!group_sync(grp)) return false;

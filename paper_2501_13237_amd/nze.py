@@ -51,6 +51,17 @@ class NzeFitOpts(ctypes.Structure):
                 ("ref_sign", ctypes.c_int32), ("b_max", ctypes.c_double)]
 
 
+class NzeJobSpec(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("chi_max", ctypes.c_int32),
+                ("n_levels", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("n_layers", ctypes.c_int32),
+                ("layer_gates", ctypes.POINTER(ctypes.c_int32)),
+                ("left_sites", ctypes.POINTER(ctypes.c_int32)),
+                ("ptm", ctypes.POINTER(ctypes.c_double)),
+                ("n_obs", ctypes.c_int32),
+                ("paulis", ctypes.POINTER(ctypes.c_uint8))]
+
+
 class NzeError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"nze error {code}: {msg}")
@@ -100,6 +111,20 @@ def lib():
         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
         c_double_p, c_int32_p, ctypes.c_void_p]
+    L.nze_server_create.argtypes = [ctypes.POINTER(ctypes.c_void_p),
+                                    ctypes.c_void_p, ctypes.c_size_t,
+                                    ctypes.c_int32, ctypes.c_void_p]
+    L.nze_server_free.argtypes = [ctypes.c_void_p]
+    L.nze_server_free.restype = None
+    L.nze_server_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(NzeJobSpec),
+                                    ctypes.POINTER(ctypes.c_int64)]
+    L.nze_server_step.argtypes = [ctypes.c_void_p, c_int32_p, c_int32_p,
+                                  c_int32_p]
+    L.nze_server_poll.argtypes = [ctypes.c_void_p, ctypes.c_int64, c_int32_p,
+                                  c_double_p, c_double_p, c_double_p]
+    L.nze_server_stats.argtypes = [ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_size_t),
+                                   ctypes.POINTER(ctypes.c_int64)]
     L.nze_fit_opts_default.argtypes = [ctypes.POINTER(NzeFitOpts)]
     L.nze_fit_opts_default.restype = None
     L.nze_extrapolate.argtypes = [ctypes.c_int32, c_double_p, c_double_p,
@@ -352,3 +377,80 @@ def run_circuit(mpo, layers, noise, factors):
     level factors."""
     for ls, us in layers:
         mpo.apply_layer(ls, layer_ptms(us, noise, factors))
+
+
+# ---------------------------------------------------------------- serving
+
+
+class Server:
+    """Continuous-batching request loop of the library (nze_server_*): jobs
+    are admitted by HBM footprint into a torch-allocated arena."""
+
+    def __init__(self, arena_bytes, max_active=64, stream=None):
+        import torch
+        self.arena = torch.empty(arena_bytes + 256, dtype=torch.uint8,
+                                 device="cuda")
+        ptr = (self.arena.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(lib().nze_server_create(ctypes.byref(h), ctypes.c_void_p(ptr),
+                                       ctypes.c_size_t(arena_bytes), max_active,
+                                       ctypes.c_void_p(self.stream.cuda_stream)))
+        self.h = h
+        self.meta = {}
+
+    def submit(self, n, chi, precision, layers, ptms, observables):
+        """layers: list of left-site arrays; ptms: list of per-layer
+        [L][gates][16][16] arrays (same length)."""
+        L = ptms[0].shape[0] if ptms else 1
+        gates = np.array([len(x) for x in layers], dtype=np.int32)
+        ls = np.ascontiguousarray(np.concatenate(
+            [np.asarray(x, dtype=np.int32) for x in layers]) if layers else
+            np.zeros(0, dtype=np.int32))
+        pt = np.ascontiguousarray(np.concatenate(
+            [np.asarray(p, dtype=np.float64).reshape(-1) for p in ptms]) if ptms
+            else np.zeros(0))
+        obs = np.ascontiguousarray(np.asarray(observables, dtype=np.uint8)
+                                   .reshape(-1, n))
+        spec = NzeJobSpec(n, chi, L, precision, len(layers),
+                          gates.ctypes.data_as(c_int32_p),
+                          ls.ctypes.data_as(c_int32_p), _dp(pt), obs.shape[0],
+                          obs.ctypes.data_as(c_uint8_p))
+        jid = ctypes.c_int64()
+        _check(lib().nze_server_submit(self.h, ctypes.byref(spec),
+                                       ctypes.byref(jid)))
+        self.meta[jid.value] = (L, obs.shape[0])
+        return jid.value
+
+    def step(self):
+        a, q, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().nze_server_step(self.h, ctypes.byref(a), ctypes.byref(q),
+                                     ctypes.byref(d)))
+        return a.value, q.value, d.value
+
+    def poll(self, jid):
+        L, n_obs = self.meta[jid]
+        st = ctypes.c_int32()
+        vals = np.zeros((L, max(n_obs, 1)))
+        fid = np.zeros(L)
+        times = np.zeros(3)
+        _check(lib().nze_server_poll(self.h, jid, ctypes.byref(st), _dp(vals),
+                                     _dp(fid), _dp(times)))
+        return st.value, vals[:, :n_obs], fid, times
+
+    def stats(self):
+        hw = ctypes.c_size_t()
+        la = ctypes.c_int64()
+        _check(lib().nze_server_stats(self.h, ctypes.byref(hw), ctypes.byref(la)))
+        return hw.value, la.value
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            lib().nze_server_free(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
