@@ -164,6 +164,74 @@ def serve_run(nze, jobs, rate, seed, precision):
             "launches": int(launches), "arena_high_water_gib": hw / 2 ** 30}
 
 
+def precision_report(nze, workloads, chis=(64, 128, 256), oracle_chis=(64,)):
+    """n = 32, depth 20, depolarizing 1e-3 + amplitude damping 5e-4, one level:
+    all <Z_i> from the mixed and float64 GPU paths and (for oracle_chis) the
+    CPU oracle."""
+    from oracle import mpo as ompo
+    from oracle import ptm as optm
+    out = []
+    for chi in chis:
+        w = workloads.mixed_n32(chi=chi, seed=0)
+        layers = w.circuit()
+        res = {}
+        for name, prec in (("mixed", nze.NZE_MIXED), ("fp64", nze.NZE_FP64)):
+            m = nze.MPO(w.n, chi, 1, prec)
+            t0 = time.perf_counter()
+            nze.run_circuit(m, layers, w.noise, w.factors)
+            vals, fid, tr = m.expect(w.observables)
+            st, _ = m.stats()
+            res[name] = (vals[0], fid[0], time.perf_counter() - t0, st[0]["min_cut_gap"])
+            m.close()
+        rec = {"chi": chi, "F_mixed": res["mixed"][1], "F_fp64": res["fp64"][1],
+               "max_abs_mixed_vs_fp64": float(np.max(np.abs(res["mixed"][0] - res["fp64"][0]))),
+               "mean_abs_mixed_vs_fp64": float(np.mean(np.abs(res["mixed"][0] - res["fp64"][0]))),
+               "min_cut_gap_fp64": res["fp64"][3],
+               "seconds_mixed": res["mixed"][2], "seconds_fp64": res["fp64"][2]}
+        if chi in oracle_chis:
+            m = ompo.PauliMPO(w.n, chi)
+            nz = optm.Noise(**w.noise)
+            for ls, us in layers:
+                m.apply_layer(ls, [optm.ptm_noisy_gate(U, nz) for U in us])
+            ref = m.expectations(w.observables)
+            rec["max_abs_mixed_vs_oracle"] = float(np.max(np.abs(res["mixed"][0] - ref)))
+            rec["max_abs_fp64_vs_oracle"] = float(np.max(np.abs(res["fp64"][0] - ref)))
+            rec["F_oracle"] = m.fidelity
+        out.append(rec)
+        print(json.dumps(rec), file=sys.stderr, flush=True)
+    return out
+
+
+def clifford_report(nze, workloads, depth=30, precision=None):
+    """n = 64 random Clifford brickwork, Pauli noise 3e-4 per qubit, six
+    levels, chi = 512: every weight-1 and nearest-neighbour weight-2 Pauli
+    against exact Pauli propagation."""
+    from oracle import pauliprop
+    from oracle import ptm as optm
+    precision = nze.NZE_MIXED if precision is None else precision
+    w = workloads.clifford_n64(seed=0)
+    w.depth = depth
+    layers = w.circuit()
+    m = nze.MPO(w.n, w.chi, len(w.factors), precision)
+    t0 = time.perf_counter()
+    nze.run_circuit(m, layers, w.noise, w.factors)
+    vals, fid, tr = m.expect(w.observables)
+    secs = time.perf_counter() - t0
+    st, bonds = m.stats()
+    gates = [(k, U) for ls, us in layers for k, U in zip(ls, us)]
+    recs = []
+    for j, c in enumerate(w.factors):
+        nz = optm.Noise(**w.noise).scaled(c)
+        ref = np.array([pauliprop.expectation(w.n, gates, nz, o) for o in w.observables])
+        nzmask = np.abs(ref) > 1e-12
+        recs.append({"factor": c, "F": float(fid[j]),
+                     "max_abs_err": float(np.max(np.abs(vals[j] - ref))),
+                     "nonzero_exact": int(nzmask.sum()),
+                     "max_abs_err_nonzero": float(np.max(np.abs(vals[j] - ref)[nzmask])) if nzmask.any() else None,
+                     "max_bond": int(st[j]["max_bond"])})
+    return {"depth": depth, "seconds": secs, "levels": recs}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,7 +246,10 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-sustainable-rate", type=float, default=0.0)
     ap.add_argument("--skip-main", action="store_true",
-                    help="only the serving runs")
+                    help="only the serving / report runs")
+    ap.add_argument("--precision-report", action="store_true")
+    ap.add_argument("--clifford-report", type=int, default=0,
+                    help="run the n=64 Clifford check at this depth")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus must be 1 "
@@ -197,10 +268,14 @@ def main():
     upd_per_job = workloads.n_gates(layers) * len(w.factors)
 
     if args.skip_main:
-        out = {"metric": "p50/p99 job latency (serving)", "unit": "s",
-               "n_gpus": 1, "data": "synthetic"}
-        jobs = serve_jobs(args.serve, 1, workloads, nze)
-        out["serving"] = serve_run(nze, jobs, args.serve_rate, 1, nze.NZE_MIXED)
+        out = {"metric": "reports", "n_gpus": 1, "data": "synthetic"}
+        if args.precision_report:
+            out["precision_n32"] = precision_report(nze, workloads)
+        if args.clifford_report:
+            out["clifford_n64"] = clifford_report(nze, workloads, args.clifford_report)
+        if args.serve:
+            jobs = serve_jobs(args.serve, 1, workloads, nze)
+            out["serving"] = serve_run(nze, jobs, args.serve_rate, 1, nze.NZE_MIXED)
         if args.serve_sustainable_rate > 0:
             out["serving_sustainable"] = serve_run(
                 nze, jobs, args.serve_sustainable_rate, 1, nze.NZE_MIXED)

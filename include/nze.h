@@ -99,9 +99,8 @@ typedef struct mpo_config {
   double jacobi_tol;   /* relative off-diagonal threshold of the one-sided
                           Jacobi SVD: rows u, v count as orthogonal when
                           |<x_u,x_v>| <= tol |x_u||x_v| + tol_abs |X| |x_max|;
-                          tol is raised to at least 8 sqrt(min(C, 64)) eps of
-                          the path (C = row length; the block Grams sum MFMA
-                          partials over 64 columns in float64);
+                          tol is raised to at least 8 sqrt(C) eps of the path
+                          (C = row length);
                           0 -> 1e-13 (FP64) / 2e-6 (mixed);
                           tol_abs is 1e-15 (FP64) / 1e-6 (mixed)             */
   int32_t max_sweeps;  /* Jacobi sweep cap (<= 40); 0 -> 30                   */
@@ -186,6 +185,13 @@ typedef struct nze_stats {
                             4 R^2 (2C + R) (block Grams plus rotation of the
                             data and of the accumulator); centre-move
                             absorption 8 r cr c2                             */
+  int64_t cap_hits;      /* SVDs that reached max_sweeps while every pair was
+                            within 1000x the tolerance (the rounding floor);
+                            beyond that mpo_expect/mpo_sync report
+                            NZE_ENOCONV                                       */
+  double cap_offdiag;    /* largest scaled off-diagonal, in units of the
+                            tolerance, in the last sweep of any SVD that
+                            reached max_sweeps (0 if none did)               */
 } nze_stats;
 
 /* Per-level statistics (synchronises the stream).
@@ -208,7 +214,8 @@ int mpo_profile(mpo_t* h, double* ms_out);
 int mpo_bond_spectrum(mpo_t* h, int32_t lv, int32_t l, double* s_out,
                       int32_t cap, int32_t* count);
 
-/* Waits for the handle's queued work and reports deferred errors. */
+/* Waits for the handle's queued work and reports deferred errors
+ * (NZE_ENOCONV, NZE_ENUM, NZE_EHIP). */
 int mpo_sync(mpo_t* h);
 
 /* -------------------------------------------------------- extrapolation */

@@ -23,10 +23,10 @@ enum { OP_NONE = 0, OP_GATE_LR = 1, OP_GATE_RL = 2, OP_MOVE_LR = 3,
 
 // per-MPO float64 scalars
 enum { SC_LOG = 0, SC_FID = 1, SC_MAXDISC = 2, SC_MINGAP = 3, SC_F2 = 4,
-       SC_KEPT = 5, SC_FLOPS = 6, SC_COUNT = 8 };
+       SC_KEPT = 5, SC_FLOPS = 6, SC_CAPQ = 7, SC_COUNT = 8 };
 // per-MPO int counters
 enum { CT_RANK = 0, CT_ERR = 1, CT_MAXSW = 2, CT_UPD = 3, CT_SWTOT = 4,
-       CT_ROT = 8, CT_COUNT = 8 + MAXSW };
+       CT_OFFMAX = 5, CT_CAPHIT = 6, CT_ROT = 8, CT_COUNT = 8 + MAXSW };
 enum { ERR_NOCONV = 1, ERR_NAN = 2, ERR_ABORT = 4 };
 
 // Everything one MPO (one noise level of one job) owns on the device.

@@ -97,6 +97,7 @@ __global__ void k_init(const Slot* slots, const double* init_sites, int n) {
     s.scal[SC_F2] = 0.0;
     s.scal[SC_KEPT] = 0.0;
     s.scal[SC_FLOPS] = 0.0;
+    s.scal[SC_CAPQ] = 0.0;
   }
 }
 
@@ -696,6 +697,8 @@ extern "C" int mpo_stats(mpo_t* h, nze_stats* stats, int32_t* bonds) {
     s.updates = ct[CT_UPD];
     s.sweeps_total = ct[CT_SWTOT];
     s.flops = sc[SC_FLOPS];
+    s.cap_hits = ct[CT_CAPHIT];
+    s.cap_offdiag = sc[SC_CAPQ];
     int mb = 0;
     for (int b = 1; b < n; ++b) {
       mb = std::max(mb, dims[(size_t)l * (n + 1) + b]);

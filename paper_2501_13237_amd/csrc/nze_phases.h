@@ -427,20 +427,24 @@ __device__ void jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
   pair_gram<T>(X, C, C, L);
   clk.lap(s.prof, PF_GRAM);
   // convergence test: |g_uv| > tol sqrt(g_uu g_vv) + tol_abs sqrt(F2 max);
-  // tol is raised to the rounding level of the block Gram (MFMA partial sums
-  // over at most 64 columns, accumulated in float64)
+  // tol is raised to the rounding level of a length-C dot product of the path
   const double eps = sizeof(T) == 4 ? 5.96e-8 : 1.11e-16;
-  const double tol = fmax(s.tol_rel, 8.0 * sqrt((double)(C < 64 ? C : 64)) * eps);
-  int need = 0;
+  const double tol = fmax(s.tol_rel, 8.0 * sqrt((double)C) * eps);
+  const double ratio_abs = s.tol_abs / tol;
+  float worst = 0.f;   // largest |g_uv| / (sqrt(g_uu g_vv) + ratio_abs sqrt(F2 max))
   for (int e = tid; e < 1024; e += NT) {
     const int u = e >> 5, v = e & 31;
     if (v <= u) continue;
     const double guu = L.Gs[u * GLD + u], gvv = L.Gs[v * GLD + v];
     const double guv = fabs(L.Gs[u * GLD + v]);
-    if (!(guv <= tol * sqrt(guu * gvv) +
-                     s.tol_abs * sqrt(F2 * fmax(guu, gvv))))
-      need = 1;
+    const double den = sqrt(guu * gvv) + ratio_abs * sqrt(F2 * fmax(guu, gvv));
+    const double q = den > 0.0 ? guv / den : (guv > 0.0 ? 1.0 : 0.0);
+    worst = fmaxf(worst, (q == q) ? float(q) : 1.0f);
   }
+  for (int o = 32; o > 0; o >>= 1) worst = fmaxf(worst, __shfl_xor(worst, o, 64));
+  const int need = worst > float(tol);
+  if ((tid & 63) == 0 && worst > 0.f)
+    atomicMax(&s.ctr[CT_OFFMAX], __float_as_int(worst));
   if (need) L.flag[1] = 1;
   __syncthreads();
   const int go = L.flag[1];
@@ -528,7 +532,10 @@ __device__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, int C, int g,
       f2 = block_sum(f2, smem + 6 * CHI_LIMIT);
       sort_rows(s, R, key, idx);
       for (int i = threadIdx.x; i < R; i += NT) s.perm[i] = idx[i];
-      if (threadIdx.x == 0) s.scal[SC_F2] = f2;
+      if (threadIdx.x == 0) {
+        s.scal[SC_F2] = f2;
+        s.ctr[CT_OFFMAX] = 0;
+      }
     }
     if (!group_sync(grp)) return false;
     const double F2 = __hip_atomic_load(&s.scal[SC_F2], __ATOMIC_RELAXED,
@@ -558,7 +565,15 @@ __device__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, int C, int g,
     s.scal[SC_FLOPS] += 4.0 * sweeps * double(R) * double(R) * (2.0 * C + R);
     s.ctr[CT_SWTOT] += sweeps;
     if (sweeps > s.ctr[CT_MAXSW]) s.ctr[CT_MAXSW] = sweeps;
-    if (!conv) s.ctr[CT_ERR] |= ERR_NOCONV;
+    if (!conv) {
+      // the cap was reached: fine at the rounding floor, an error beyond it
+      const double eps = sizeof(T) == 4 ? 5.96e-8 : 1.11e-16;
+      const double tol = fmax(s.tol_rel, 8.0 * sqrt((double)C) * eps);
+      const float worst = __int_as_float(s.ctr[CT_OFFMAX]);
+      s.scal[SC_CAPQ] = fmax(s.scal[SC_CAPQ], double(worst) / tol);
+      if (double(worst) > 1e3 * tol) s.ctr[CT_ERR] |= ERR_NOCONV;
+      else s.ctr[CT_CAPHIT] += 1;
+    }
   }
   return true;
 }

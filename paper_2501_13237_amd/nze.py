@@ -41,7 +41,8 @@ class NzeStats(ctypes.Structure):
                 ("min_cut_gap", ctypes.c_double),
                 ("max_bond", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("updates", ctypes.c_int64), ("sweeps_total", ctypes.c_int64),
-                ("flops", ctypes.c_double)]
+                ("flops", ctypes.c_double), ("cap_hits", ctypes.c_int64),
+                ("cap_offdiag", ctypes.c_double)]
 
 
 class NzeFitOpts(ctypes.Structure):
@@ -331,7 +332,8 @@ class MPO:
                      max_discarded=s.max_discarded,
                      min_cut_gap=s.min_cut_gap, max_bond=s.max_bond,
                      max_sweeps=s.max_sweeps, updates=s.updates,
-                     sweeps_total=s.sweeps_total, flops=s.flops)
+                     sweeps_total=s.sweeps_total, flops=s.flops,
+                     cap_hits=s.cap_hits, cap_offdiag=s.cap_offdiag)
                 for s in st], bonds
 
     PROFILE_NAMES = ["theta", "gram", "check", "eigh", "rot_x", "rot_w",
