@@ -202,34 +202,70 @@ def precision_report(nze, workloads, chis=(64, 128, 256), oracle_chis=(64,)):
     return out
 
 
-def clifford_report(nze, workloads, depth=30, precision=None):
+def clifford_report(nze, workloads, depth=30, precision=None, mirror=False):
     """n = 64 random Clifford brickwork, Pauli noise 3e-4 per qubit, six
     levels, chi = 512: every weight-1 and nearest-neighbour weight-2 Pauli
-    against exact Pauli propagation."""
+    against exact Pauli propagation.  mirror: depth/2 random layers followed
+    by their inverses, whose <Z_i> are nonzero products of noise factors."""
     from oracle import pauliprop
     from oracle import ptm as optm
     precision = nze.NZE_MIXED if precision is None else precision
     w = workloads.clifford_n64(seed=0)
-    w.depth = depth
-    layers = w.circuit()
+    if mirror:
+        w.depth = depth // 2
+        half = w.circuit()
+        layers = half + [(ls, [np.ascontiguousarray(U.conj().T) for U in us])
+                         for ls, us in reversed(half)]
+    else:
+        w.depth = depth
+        layers = w.circuit()
     m = nze.MPO(w.n, w.chi, len(w.factors), precision)
     t0 = time.perf_counter()
-    nze.run_circuit(m, layers, w.noise, w.factors)
+    for t, (ls, us) in enumerate(layers):
+        m.apply_layer(ls, nze.layer_ptms(us, w.noise, w.factors))
+        m.sync()
+        print(f"clifford layer {t + 1}/{len(layers)} at {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
     vals, fid, tr = m.expect(w.observables)
     secs = time.perf_counter() - t0
     st, bonds = m.stats()
+    m.close()
     gates = [(k, U) for ls, us in layers for k, U in zip(ls, us)]
+    tables = pauliprop.gate_tables(gates)
     recs = []
     for j, c in enumerate(w.factors):
         nz = optm.Noise(**w.noise).scaled(c)
-        ref = np.array([pauliprop.expectation(w.n, gates, nz, o) for o in w.observables])
-        nzmask = np.abs(ref) > 1e-12
-        recs.append({"factor": c, "F": float(fid[j]),
-                     "max_abs_err": float(np.max(np.abs(vals[j] - ref))),
-                     "nonzero_exact": int(nzmask.sum()),
-                     "max_abs_err_nonzero": float(np.max(np.abs(vals[j] - ref)[nzmask])) if nzmask.any() else None,
-                     "max_bond": int(st[j]["max_bond"])})
-    return {"depth": depth, "seconds": secs, "levels": recs}
+        ref = np.array([pauliprop.expectation(w.n, gates, nz, o, tables=tables)
+                        for o in w.observables])
+        print(f"clifford exact level {j + 1}/{len(w.factors)} done", file=sys.stderr, flush=True)
+        fin = np.isfinite(vals[j])
+        nzmask = (np.abs(ref) > 1e-12) & fin
+        err = np.abs(vals[j] - ref)
+        recs.append({"factor": c, "F": float(fid[j]), "trace": float(tr[j]),
+                     "non_finite": int((~fin).sum()),
+                     "max_abs_err": float(np.max(err[fin])) if fin.any() else None,
+                     "nonzero_exact": int((np.abs(ref) > 1e-12).sum()),
+                     "max_abs_err_nonzero": float(np.max(err[nzmask])) if nzmask.any() else None,
+                     "max_bond": int(st[j]["max_bond"]),
+                     "updates": int(st[j]["updates"])})
+    # NZNE: quadratic fit over the six levels, evaluated at zero noise,
+    # against the noiseless exact value (observables finite at every level)
+    lam = np.array(w.factors) * w.noise["px"]
+    exact0 = np.array([pauliprop.expectation(w.n, gates, optm.Noise(), o, tables=tables)
+                       for o in w.observables])
+    ok = np.all(np.isfinite(vals), axis=0)
+    zne = np.full(vals.shape[1], np.nan)
+    for i in np.nonzero(ok)[0]:
+        zne[i] = nze.extrapolate(lam, vals[:, i], fid)[0]
+    nz0 = (np.abs(exact0) > 1e-12) & ok
+    e0 = np.abs(zne - exact0)
+    return {"variant": "mirror" if mirror else "random", "depth": len(layers),
+            "seconds": secs, "updates_per_s": sum(r["updates"] for r in recs) / secs,
+            "levels": recs, "observables_finite_at_all_levels": int(ok.sum()),
+            "nzne_max_abs_err": float(np.max(e0[ok])) if ok.any() else None,
+            "nzne_max_abs_err_nonzero": float(np.max(e0[nz0])) if nz0.any() else None,
+            "level1_max_abs_err_nonzero": float(np.max(np.abs(vals[0] - exact0)[nz0])) if nz0.any() else None,
+            "nonzero_exact_noiseless": int((np.abs(exact0) > 1e-12).sum())}
 
 
 def main():
@@ -250,6 +286,8 @@ def main():
     ap.add_argument("--precision-report", action="store_true")
     ap.add_argument("--clifford-report", type=int, default=0,
                     help="run the n=64 Clifford check at this depth")
+    ap.add_argument("--clifford-mirror", action="store_true",
+                    help="Clifford check on half the depth plus its inverse")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus must be 1 "
@@ -272,7 +310,8 @@ def main():
         if args.precision_report:
             out["precision_n32"] = precision_report(nze, workloads)
         if args.clifford_report:
-            out["clifford_n64"] = clifford_report(nze, workloads, args.clifford_report)
+            out["clifford_n64"] = clifford_report(nze, workloads, args.clifford_report,
+                                                  mirror=args.clifford_mirror)
         if args.serve:
             jobs = serve_jobs(args.serve, 1, workloads, nze)
             out["serving"] = serve_run(nze, jobs, args.serve_rate, 1, nze.NZE_MIXED)

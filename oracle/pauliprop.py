@@ -52,22 +52,25 @@ def channel_eigenvalues(kraus_list_seq):
     return f
 
 
-def expectation(n, gates, noise, paulis, init_bits=None):
+def gate_tables(gates):
+    """conjugation_table of every gate of a flat (k, U) list, in order."""
+    return [conjugation_table(U) for _, U in gates]
+
+
+def expectation(n, gates, noise, paulis, init_bits=None, tables=None):
     """Exact <paulis> after the gate sequence ``gates`` (a flat list of
     (k, U) in application order, gate on qubits (k, k+1)) with ``noise`` after
-    every gate, starting from the product state |init_bits>."""
+    every gate, starting from the product state |init_bits>.  ``tables`` may
+    hold gate_tables(gates) when many strings share one circuit."""
     init_bits = init_bits if init_bits is not None else [0] * n
     f = channel_eigenvalues(noise_kraus_sequence(noise))
+    tables = tables if tables is not None else gate_tables(gates)
     string = list(paulis)
     coef = 1.0
-    cache = {}
-    for k, U in reversed(gates):
-        key = id(U)
-        if key not in cache:
-            cache[key] = conjugation_table(U)
+    for (k, _), table in zip(reversed(gates), reversed(tables)):
         P = 4 * string[k] + string[k + 1]
         coef *= f[P]                       # N^dag first ...
-        Q, sign = cache[key][P]            # ... then U^dag . U
+        Q, sign = table[P]                 # ... then U^dag . U
         coef *= sign
         string[k], string[k + 1] = Q // 4, Q % 4
     for q, p in enumerate(string):
