@@ -164,108 +164,50 @@ def serve_run(nze, jobs, rate, seed, precision):
             "launches": int(launches), "arena_high_water_gib": hw / 2 ** 30}
 
 
-def precision_report(nze, workloads, chis=(64, 128, 256), oracle_chis=(64,)):
-    """n = 32, depth 20, depolarizing 1e-3 + amplitude damping 5e-4, one level:
-    all <Z_i> from the mixed and float64 GPU paths and (for oracle_chis) the
-    CPU oracle."""
-    from oracle import mpo as ompo
-    from oracle import ptm as optm
-    out = []
-    for chi in chis:
-        w = workloads.mixed_n32(chi=chi, seed=0)
-        layers = w.circuit()
-        res = {}
-        for name, prec in (("mixed", nze.NZE_MIXED), ("fp64", nze.NZE_FP64)):
-            m = nze.MPO(w.n, chi, 1, prec)
-            t0 = time.perf_counter()
-            nze.run_circuit(m, layers, w.noise, w.factors)
-            vals, fid, tr = m.expect(w.observables)
-            st, _ = m.stats()
-            res[name] = (vals[0], fid[0], time.perf_counter() - t0, st[0]["min_cut_gap"])
-            m.close()
-        rec = {"chi": chi, "F_mixed": res["mixed"][1], "F_fp64": res["fp64"][1],
-               "max_abs_mixed_vs_fp64": float(np.max(np.abs(res["mixed"][0] - res["fp64"][0]))),
-               "mean_abs_mixed_vs_fp64": float(np.mean(np.abs(res["mixed"][0] - res["fp64"][0]))),
-               "min_cut_gap_fp64": res["fp64"][3],
-               "seconds_mixed": res["mixed"][2], "seconds_fp64": res["fp64"][2]}
-        if chi in oracle_chis:
-            m = ompo.PauliMPO(w.n, chi)
-            nz = optm.Noise(**w.noise)
-            for ls, us in layers:
-                m.apply_layer(ls, [optm.ptm_noisy_gate(U, nz) for U in us])
-            ref = m.expectations(w.observables)
-            rec["max_abs_mixed_vs_oracle"] = float(np.max(np.abs(res["mixed"][0] - ref)))
-            rec["max_abs_fp64_vs_oracle"] = float(np.max(np.abs(res["fp64"][0] - ref)))
-            rec["F_oracle"] = m.fidelity
-        out.append(rec)
-        print(json.dumps(rec), file=sys.stderr, flush=True)
+def copy_probe(torch, mib):
+    """A plain device copy of known size: the HBM counters of one dispatch
+    read mib MiB fetched and mib MiB written when they count exactly."""
+    torch.cuda.set_device(0)
+    x = torch.ones(mib * 2 ** 18, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_mib": mib, "bytes_read": mib * 2 ** 20,
+                      "bytes_written": mib * 2 ** 20}), flush=True)
+
+
+def extrapolation_error(nze, workloads):
+    """n = 8 workload (exact at chi = 256): quadratic NZNE from the GPU path
+    against the dense density-matrix values stored with the tests, under both
+    readings of the extrapolation: (i) fit levels {2,4,8}p, evaluate at p;
+    (ii) fit {1,2,4,8}p, evaluate at zero noise."""
+    path = os.path.join(ROOT, "tests", "golden", "n8_dense_exact.json")
+    with open(path) as f:
+        ref = json.load(f)
+    w = workloads.plain_fp64_n8(seed=0)
+    layers = w.circuit()
+    out = {"workload": ref["workload"]}
+    for name, prec in (("fp64", nze.NZE_FP64), ("mixed", nze.NZE_MIXED)):
+        m = nze.MPO(w.n, w.chi, len(w.factors), prec)
+        nze.run_circuit(m, layers, w.noise, w.factors)
+        vals, fid, _ = m.expect(w.observables)
+        m.close()
+        p = w.noise["dep"]
+        lam = np.array(w.factors) * p
+        ea, eb, e_raw_p, e_raw_0 = [], [], [], []
+        for o in range(len(w.observables)):
+            va, *_ = nze.extrapolate(lam[1:], vals[1:, o], fid[1:], p, nze.NZE_POLY, degree=2)
+            vb, *_ = nze.extrapolate(lam, vals[:, o], fid, 0.0, nze.NZE_POLY, degree=2)
+            ea.append(abs(va - ref["exact_at_p"][o]))
+            eb.append(abs(vb - ref["exact_noiseless"][o]))
+            e_raw_p.append(abs(vals[1, o] - ref["exact_at_p"][o]))
+            e_raw_0.append(abs(vals[0, o] - ref["exact_noiseless"][o]))
+        out[name] = {"nzne_levels_2_4_8_to_p_max_abs_err": max(ea),
+                     "unmitigated_2p_vs_p_max_abs_err": max(e_raw_p),
+                     "zne_levels_1_2_4_8_to_0_max_abs_err": max(eb),
+                     "unmitigated_p_vs_0_max_abs_err": max(e_raw_0)}
     return out
-
-
-def clifford_report(nze, workloads, depth=30, precision=None, mirror=False):
-    """n = 64 random Clifford brickwork, Pauli noise 3e-4 per qubit, six
-    levels, chi = 512: every weight-1 and nearest-neighbour weight-2 Pauli
-    against exact Pauli propagation.  mirror: depth/2 random layers followed
-    by their inverses, whose <Z_i> are nonzero products of noise factors."""
-    from oracle import pauliprop
-    from oracle import ptm as optm
-    precision = nze.NZE_MIXED if precision is None else precision
-    w = workloads.clifford_n64(seed=0)
-    if mirror:
-        w.depth = depth // 2
-        half = w.circuit()
-        layers = half + [(ls, [np.ascontiguousarray(U.conj().T) for U in us])
-                         for ls, us in reversed(half)]
-    else:
-        w.depth = depth
-        layers = w.circuit()
-    m = nze.MPO(w.n, w.chi, len(w.factors), precision)
-    t0 = time.perf_counter()
-    for t, (ls, us) in enumerate(layers):
-        m.apply_layer(ls, nze.layer_ptms(us, w.noise, w.factors))
-        m.sync()
-        print(f"clifford layer {t + 1}/{len(layers)} at {time.perf_counter() - t0:.1f} s",
-              file=sys.stderr, flush=True)
-    vals, fid, tr = m.expect(w.observables)
-    secs = time.perf_counter() - t0
-    st, bonds = m.stats()
-    m.close()
-    gates = [(k, U) for ls, us in layers for k, U in zip(ls, us)]
-    tables = pauliprop.gate_tables(gates)
-    recs = []
-    for j, c in enumerate(w.factors):
-        nz = optm.Noise(**w.noise).scaled(c)
-        ref = np.array([pauliprop.expectation(w.n, gates, nz, o, tables=tables)
-                        for o in w.observables])
-        print(f"clifford exact level {j + 1}/{len(w.factors)} done", file=sys.stderr, flush=True)
-        fin = np.isfinite(vals[j])
-        nzmask = (np.abs(ref) > 1e-12) & fin
-        err = np.abs(vals[j] - ref)
-        recs.append({"factor": c, "F": float(fid[j]), "trace": float(tr[j]),
-                     "non_finite": int((~fin).sum()),
-                     "max_abs_err": float(np.max(err[fin])) if fin.any() else None,
-                     "nonzero_exact": int((np.abs(ref) > 1e-12).sum()),
-                     "max_abs_err_nonzero": float(np.max(err[nzmask])) if nzmask.any() else None,
-                     "max_bond": int(st[j]["max_bond"]),
-                     "updates": int(st[j]["updates"])})
-    # NZNE: quadratic fit over the six levels, evaluated at zero noise,
-    # against the noiseless exact value (observables finite at every level)
-    lam = np.array(w.factors) * w.noise["px"]
-    exact0 = np.array([pauliprop.expectation(w.n, gates, optm.Noise(), o, tables=tables)
-                       for o in w.observables])
-    ok = np.all(np.isfinite(vals), axis=0)
-    zne = np.full(vals.shape[1], np.nan)
-    for i in np.nonzero(ok)[0]:
-        zne[i] = nze.extrapolate(lam, vals[:, i], fid)[0]
-    nz0 = (np.abs(exact0) > 1e-12) & ok
-    e0 = np.abs(zne - exact0)
-    return {"variant": "mirror" if mirror else "random", "depth": len(layers),
-            "seconds": secs, "updates_per_s": sum(r["updates"] for r in recs) / secs,
-            "levels": recs, "observables_finite_at_all_levels": int(ok.sum()),
-            "nzne_max_abs_err": float(np.max(e0[ok])) if ok.any() else None,
-            "nzne_max_abs_err_nonzero": float(np.max(e0[nz0])) if nz0.any() else None,
-            "level1_max_abs_err_nonzero": float(np.max(np.abs(vals[0] - exact0)[nz0])) if nz0.any() else None,
-            "nonzero_exact_noiseless": int((np.abs(exact0) > 1e-12).sum())}
 
 
 def main():
@@ -282,20 +224,21 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-sustainable-rate", type=float, default=0.0)
     ap.add_argument("--skip-main", action="store_true",
-                    help="only the serving / report runs")
-    ap.add_argument("--precision-report", action="store_true")
-    ap.add_argument("--clifford-report", type=int, default=0,
-                    help="run the n=64 Clifford check at this depth")
-    ap.add_argument("--clifford-mirror", action="store_true",
-                    help="Clifford check on half the depth plus its inverse")
+                    help="only the serving runs")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only copy this many MiB device-to-device five times "
+                         "(calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU; --gpus must be 1 "
-              "(the levels and jobs of a multi-GPU run would be sharded "
-              "without communication, see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU only (--gpus 1): the levels and jobs "
+              "of a multi-GPU run shard across GPUs without communication, so "
+              "the one-GPU throughput is the per-GPU share", file=sys.stderr)
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        copy_probe(torch, args.copy_probe)
+        return
     from paper_2501_13237_amd import nze, workloads
     torch.cuda.set_device(0)
     nze.lib()
@@ -307,15 +250,11 @@ def main():
 
     if args.skip_main:
         out = {"metric": "reports", "n_gpus": 1, "data": "synthetic"}
-        if args.precision_report:
-            out["precision_n32"] = precision_report(nze, workloads)
-        if args.clifford_report:
-            out["clifford_n64"] = clifford_report(nze, workloads, args.clifford_report,
-                                                  mirror=args.clifford_mirror)
         if args.serve:
             jobs = serve_jobs(args.serve, 1, workloads, nze)
             out["serving"] = serve_run(nze, jobs, args.serve_rate, 1, nze.NZE_MIXED)
         if args.serve_sustainable_rate > 0:
+            jobs = jobs if args.serve else serve_jobs(200, 1, workloads, nze)
             out["serving_sustainable"] = serve_run(
                 nze, jobs, args.serve_sustainable_rate, 1, nze.NZE_MIXED)
         print(json.dumps(out), flush=True)
@@ -383,6 +322,7 @@ def main():
         out["speedup_mixed_vs_fp64"] = value / v64
         out["mixed_vs_fp64_max_abs_obs"] = float(np.max(np.abs(vals - vals64)))
         out["mixed_vs_fp64_max_rel_fid"] = float(np.max(np.abs(fid - fid64) / fid64))
+    out["extrapolation_error_n8"] = extrapolation_error(nze, workloads)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, layers)
     print(json.dumps(out), flush=True)

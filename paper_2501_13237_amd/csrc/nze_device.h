@@ -131,17 +131,28 @@ struct Group {
   int nbar;
   uint64_t timeout;
   int* sflag;   // one LDS int
+  int local;    // every workgroup of the group runs on one XCD
 };
+
+// XCD (accelerator complex die) this wave runs on.
+__device__ inline int xcc_id() {
+  unsigned v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return (int)(v & 7u);
+}
 
 __device__ inline bool group_sync(Group& grp) {
   // every wave's global stores have completed before the workgroup barrier;
-  // thread 0 then publishes them device-wide (release), arrives, waits, and
-  // acquires (the vector L1 it invalidates is shared by the whole workgroup)
+  // thread 0 then publishes them (release), arrives, waits, and acquires (the
+  // vector L1 it invalidates is shared by the whole workgroup).  A group on
+  // one XCD shares that XCD's L2, where the completed stores already are:
+  // release is the store wait alone and acquire invalidates the L1 only,
+  // instead of writing back and invalidating the whole L2.
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   grp.nbar += 1;
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (!grp.local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     atomicAdd(grp.bar, 1);
     const int target = grp.nbar * grp.G;
     int ok = 1;
@@ -157,7 +168,8 @@ __device__ inline bool group_sync(Group& grp) {
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (grp.local) asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
+    else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *grp.sflag = ok;
   }
   __syncthreads();

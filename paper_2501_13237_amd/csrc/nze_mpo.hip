@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -22,21 +23,61 @@ __device__ inline int ld_agent(const int* p) {
 // ------------------------------------------------------------- kernels
 
 // One launch applies a whole layer: every MPO of the batch walks through its
-// list of steps (centre moves and gates) with G workgroups; workgroup b serves
-// MPO b % nmpo, so with 8 MPOs each MPO's workgroups share one XCD.
+// list of steps (centre moves and gates) with a group of workgroups.
+//   xcd == 0: workgroup b serves MPO b % nmpo with G per MPO, device-scope
+//             group barriers.
+//   xcd == 1 (nmpo a multiple of 8): MPO m is served by workgroups running on
+//             XCD m % 8, identified by the hardware XCC_ID and numbered by
+//             arrival; after one census of the whole grid each XCD splits its
+//             workgroups evenly over its MPOs, and group barriers stay inside
+//             the XCD's L2.
+// bar: [nmpo] group counters, then 8 per-XCD tickets and the census counter.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_layer(const Slot* slots,
                                              const Step* steps,
                                              const double* ptms, int nsteps,
                                              int nmpo, int G, int* bar,
                                              int* abort_flag,
-                                             unsigned long long timeout) {
+                                             unsigned long long timeout,
+                                             int xcd) {
   __shared__ double smem[SMEM_DOUBLES];
-  __shared__ int sflag[2];
-  const int mpo = blockIdx.x % nmpo;
-  const int g = blockIdx.x / nmpo;
+  __shared__ int sflag[4];
+  int mpo = blockIdx.x % nmpo;
+  int g = blockIdx.x / nmpo;
+  if (xcd) {
+    int* tick = bar + nmpo;
+    int* census = bar + nmpo + 8;
+    if (threadIdx.x == 0) {
+      const int x = xcc_id();
+      const int j = atomicAdd(tick + x, 1);
+      atomicAdd(census, 1);
+      int ok = 1;
+      const uint64_t t0 = wall_clock64();
+      while (ld_agent(census) < (int)gridDim.x) {
+        if (ld_agent(abort_flag)) { ok = 0; break; }
+        if (wall_clock64() - t0 > timeout) { atomicExch(abort_flag, 1); ok = 0; break; }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      const int per = nmpo / 8;                 // MPOs on this XCD
+      const int gx = ld_agent(tick + x) / per;  // workgroups per MPO here
+      sflag[1] = x + 8 * (j % per);
+      sflag[2] = j / per;
+      sflag[3] = ok ? gx : 0;
+    }
+    __syncthreads();
+    mpo = sflag[1];
+    g = sflag[2];
+    G = sflag[3];
+    __syncthreads();
+    if (G == 0) {
+      // census timed out, or this XCD has fewer workgroups than MPOs
+      if (threadIdx.x == 0) atomicOr(&slots[mpo].ctr[CT_ERR], ERR_ABORT);
+      return;
+    }
+    if (g >= G) return;                         // surplus workgroup
+  }
   const Slot s = slots[mpo];
-  Group grp{bar + mpo, abort_flag, G, 0, timeout, sflag};
+  Group grp{bar + mpo, abort_flag, G, 0, timeout, sflag, xcd};
   for (int st = 0; st < nsteps; ++st) {
     const Step op = steps[(size_t)st * nmpo + mpo];
     bool ok = true;
@@ -289,6 +330,7 @@ struct DevInfo {
   int cus = 0;
   int occ[2] = {0, 0};
   unsigned long long timeout_ticks = 0;
+  bool xcd_local = false;   // 8 XCDs with their own L2 (gfx950)
 };
 std::mutex g_dev_mu;
 std::map<int, DevInfo> g_dev;
@@ -332,6 +374,11 @@ int dev_info(DevInfo& out) {
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
     khz = 100000;
   di.timeout_ticks = (unsigned long long)khz * 1000ull * 4ull;   // 4 s
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, dev));
+  const char* env = std::getenv("NZE_XCD_LOCAL");
+  di.xcd_local = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 && di.cus % 8 == 0 &&
+                 !(env && env[0] == '0');
   g_dev[dev] = di;
   out = di;
   return NZE_OK;
@@ -560,7 +607,7 @@ extern "C" int mpo_apply_layer_batch(mpo_t* const* hs, int32_t k,
   const size_t off_steps = align_up(sizeof(Slot) * nmpo);
   const size_t off_ptm = off_steps + align_up(sizeof(Step) * nsteps * nmpo);
   const size_t off_bar = off_ptm + align_up(8 * 256 * std::max<size_t>(nptm, 1));
-  const size_t total = off_bar + align_up(4 * (nmpo + 1));
+  const size_t total = off_bar + align_up(4 * (nmpo + 10));
   std::vector<char> blob(total, 0);
   Slot* bslots = reinterpret_cast<Slot*>(blob.data());
   Step* bsteps = reinterpret_cast<Step*>(blob.data() + off_steps);
@@ -588,15 +635,18 @@ extern "C" int mpo_apply_layer_batch(mpo_t* const* hs, int32_t k,
     return rc;
   }
   int* dbar = reinterpret_cast<int*>(dev + off_bar);
-  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(256), 0, stream, dbar, (int)nmpo + 1, 0);
+  hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(256), 0, stream, dbar, (int)nmpo + 10, 0);
   const Slot* a_slots = reinterpret_cast<const Slot*>(dev);
   const Step* a_steps = reinterpret_cast<const Step*>(dev + off_steps);
   const double* a_ptm = reinterpret_cast<const double*>(dev + off_ptm);
   int a_nsteps = (int)nsteps, a_nmpo = (int)nmpo, a_G = G;
-  int* a_bar = dbar;
-  int* a_abort = dbar + nmpo;
+  int* a_bar = dbar;                 // nmpo group counters, 8 tickets, census
+  int* a_abort = dbar + nmpo + 9;
   unsigned long long a_to = di.timeout_ticks;
-  void* args[] = {&a_slots, &a_steps, &a_ptm, &a_nsteps, &a_nmpo, &a_G, &a_bar, &a_abort, &a_to};
+  // XCD-local groups: every XCD hosts nmpo / 8 whole MPOs (the grid of
+  // nmpo * G workgroups is spread evenly over the 8 XCDs)
+  int a_xcd = (di.xcd_local && nmpo % 8 == 0) ? 1 : 0;
+  void* args[] = {&a_slots, &a_steps, &a_ptm, &a_nsteps, &a_nmpo, &a_G, &a_bar, &a_abort, &a_to, &a_xcd};
   const void* fn = prec == NZE_FP64 ? reinterpret_cast<const void*>(&k_layer<double>)
                                     : reinterpret_cast<const void*>(&k_layer<float>);
   HIPCHK(hipLaunchCooperativeKernel(fn, dim3((unsigned)(nmpo * G)), dim3(NT), args, 0, stream));
@@ -750,7 +800,7 @@ __global__ __launch_bounds__(NT) void k_rowortho(Slot s, int R, int C, int G,
                                                  unsigned long long to) {
   __shared__ double smem[SMEM_DOUBLES];
   __shared__ int sflag[2];
-  Group grp{bar, abort_flag, G, 0, to, sflag};
+  Group grp{bar, abort_flag, G, 0, to, sflag, 0};
   const int g = blockIdx.x;
   T* X = reinterpret_cast<T*>(s.X);
   T* W = reinterpret_cast<T*>(s.W);

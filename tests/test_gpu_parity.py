@@ -162,6 +162,27 @@ def test_batch_matches_separate_bitwise():
     assert np.array_equal(vb, rb) and np.array_equal(fb, rfb)
 
 
+@pytest.mark.parametrize("precision", [nze.NZE_FP64, nze.NZE_MIXED])
+def test_xcd_groups_match_device_groups_bitwise(precision):
+    # eight levels in one launch take the XCD-local workgroup groups; each
+    # level alone (one MPO) takes device-wide groups.  A pair visit computes
+    # the same numbers whichever workgroup runs it, so both must agree bitwise.
+    n = 12
+    layers = workloads.brickwork(n, 8, seed=31)
+    obs = workloads.z_singles(n) + workloads.zz_neighbours(n)
+    noise = {"dep": 2e-3}
+    factors = [1.0 + 15.0 * j / 7 for j in range(8)]
+    _say(f"xcd vs device groups prec={precision}")
+    m8 = _gpu_run(n, layers, noise, factors, 24, precision)
+    v8, f8, t8 = m8.expect(obs)
+    st8, _ = m8.stats()
+    assert min(s["fidelity"] for s in st8) < 0.999     # truncation happened
+    for j, c in enumerate(factors):
+        m1 = _gpu_run(n, layers, noise, [c], 24, precision)
+        v1, f1, t1 = m1.expect(obs)
+        assert np.array_equal(v8[j], v1[0]) and f8[j] == f1[0] and t8[j] == t1[0]
+
+
 def test_invalid_layer_rejected():
     m = nze.MPO(6, 8, 1, nze.NZE_FP64)
     with pytest.raises(nze.NzeError) as e:
