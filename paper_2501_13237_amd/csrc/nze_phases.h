@@ -267,12 +267,6 @@ __device__ void pair_gram(const T* X, int ld, int C, const PairLds& L) {
 // Reciprocal and reciprocal square root: hardware seeds (v_rcp_f64,
 // v_rsq_f64) refined by two Newton-Raphson steps, x_{k+1} = x_k (2 - a x_k)
 // and y_{k+1} = y_k (3 - a y_k^2) / 2; each step squares the relative error.
-__device__ inline double nr_rcp(double a) {
-  double x = __builtin_amdgcn_rcp(a);
-  x = x * fma(-a, x, 2.0);
-  x = x * fma(-a, x, 2.0);
-  return x;
-}
 __device__ inline double nr_rsq(double a) {
   double y = __builtin_amdgcn_rsq(a);
   y = y * fma(-0.5 * a * y, y, 1.5);
@@ -290,9 +284,14 @@ __device__ inline void jacobi_cs(double gpp, double gqq, double gpq,
   sn = 0.0;
   const double a2 = gpq * gpq;
   if (fabs(gpq) > floor_abs && a2 > 1e-30 * fabs(gpp * gqq)) {
-    const double tau = (gqq - gpp) * nr_rcp(2.0 * gpq);
+    // t = tan(theta) only sets how much of g_pq the rotation removes: the
+    // hardware reciprocal and root (about 1e-7 relative) leave ~1e-7 g_pq,
+    // which the next visit removes.  c must make (c, t c) orthonormal to
+    // rounding, so its root is Newton-refined.
+    const double tau = (gqq - gpp) * __builtin_amdgcn_rcp(2.0 * gpq);
     const double u = fma(tau, tau, 1.0);
-    const double t = (tau >= 0 ? 1.0 : -1.0) * nr_rcp(fabs(tau) + u * nr_rsq(u));
+    const double t = (tau >= 0 ? 1.0 : -1.0) *
+                     __builtin_amdgcn_rcp(fabs(tau) + u * __builtin_amdgcn_rsq(u));
     c = nr_rsq(fma(t, t, 1.0));
     sn = t * c;
   }
@@ -330,22 +329,26 @@ __device__ int inner_eigh(const PairLds& L, int max_inner) {
       int p, q, p2, q2;
       rr_pair32(P, st, p, q);
       rr_pair32(P2, st, p2, q2);
-      double c, sn, c2, s2;
-      jacobi_cs(Ga[p * GLD + p], Ga[q * GLD + q], Ga[p * GLD + q], floor_abs, c, sn);
-      if (P2 == P) { c2 = c; s2 = sn; }
-      else jacobi_cs(Ga[p2 * GLD + p2], Ga[q2 * GLD + q2], Ga[p2 * GLD + q2], floor_abs, c2, s2);
-      any |= (sn != 0.0);
+      // every LDS read of the step is issued before any write (the thread's
+      // four Q entries are its own within the step)
+      const int u0 = 2 * P;
+      const double gpp = Ga[p * GLD + p], gqq = Ga[q * GLD + q], gpq = Ga[p * GLD + q];
+      const double hpp = Ga[p2 * GLD + p2], hqq = Ga[q2 * GLD + q2], hpq = Ga[p2 * GLD + q2];
       const double g11 = Ga[p * GLD + p2], g12 = Ga[p * GLD + q2];
       const double g21 = Ga[q * GLD + p2], g22 = Ga[q * GLD + q2];
+      const double qa = L.Qs[u0 * GLD + p2], qb = L.Qs[u0 * GLD + q2];
+      const double qc = L.Qs[(u0 + 1) * GLD + p2], qd = L.Qs[(u0 + 1) * GLD + q2];
+      double c, sn, c2, s2;
+      jacobi_cs(gpp, gqq, gpq, floor_abs, c, sn);
+      if (P2 == P) { c2 = c; s2 = sn; }
+      else jacobi_cs(hpp, hqq, hpq, floor_abs, c2, s2);
+      any |= (sn != 0.0);
       const double h11 = c * g11 - sn * g21, h12 = c * g12 - sn * g22;
       const double h21 = sn * g11 + c * g21, h22 = sn * g12 + c * g22;
       Gb[p * GLD + p2] = c2 * h11 - s2 * h12;
       Gb[p * GLD + q2] = s2 * h11 + c2 * h12;
       Gb[q * GLD + p2] = c2 * h21 - s2 * h22;
       Gb[q * GLD + q2] = s2 * h21 + c2 * h22;
-      const int u0 = 2 * P;
-      const double qa = L.Qs[u0 * GLD + p2], qb = L.Qs[u0 * GLD + q2];
-      const double qc = L.Qs[(u0 + 1) * GLD + p2], qd = L.Qs[(u0 + 1) * GLD + q2];
       L.Qs[u0 * GLD + p2] = c2 * qa - s2 * qb;
       L.Qs[u0 * GLD + q2] = s2 * qa + c2 * qb;
       L.Qs[(u0 + 1) * GLD + p2] = c2 * qc - s2 * qd;
@@ -353,6 +356,7 @@ __device__ int inner_eigh(const PairLds& L, int max_inner) {
       double* t = Ga; Ga = Gb; Gb = t;
       __syncthreads();
     }
+    if (sw + 1 >= max_inner) break;
     if (tid == 0) L.flag[0] = 0;
     __syncthreads();
     if (any) L.flag[0] = 1;
