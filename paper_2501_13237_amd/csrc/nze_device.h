@@ -26,7 +26,8 @@ enum { SC_LOG = 0, SC_FID = 1, SC_MAXDISC = 2, SC_MINGAP = 3, SC_F2 = 4,
        SC_KEPT = 5, SC_FLOPS = 6, SC_CAPQ = 7, SC_COUNT = 8 };
 // per-MPO int counters
 enum { CT_RANK = 0, CT_ERR = 1, CT_MAXSW = 2, CT_UPD = 3, CT_SWTOT = 4,
-       CT_OFFMAX = 5, CT_CAPHIT = 6, CT_ROT = 8, CT_COUNT = 8 + MAXSW };
+       CT_OFFMAX = 5, CT_CAPHIT = 6, CT_ROT = 8, CT_BVER = 8 + MAXSW,
+       CT_COUNT = CT_BVER + 136 };   // CT_BVER: visit counters of <= 136 row blocks
 enum { ERR_NOCONV = 1, ERR_NAN = 2, ERR_ABORT = 4 };
 
 // Everything one MPO (one noise level of one job) owns on the device.
@@ -176,6 +177,53 @@ __device__ inline bool group_sync(Group& grp) {
   const int ok = *grp.sflag;
   __syncthreads();
   return ok != 0;
+}
+
+// Dataflow between the pair visits of a Jacobi sweep: ver[b] counts the
+// visits of row block b.  A visit of round t may start once both of its
+// blocks have completed round t - 1 (ver >= base + t), instead of waiting
+// for every pair of the round.
+__device__ inline bool blocks_wait(Group& grp, const int* ver, int I, int J,
+                                   int target) {
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    auto ready = [&]() {
+      return __hip_atomic_load(ver + I, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target &&
+             __hip_atomic_load(ver + J, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
+    };
+    if (!ready()) {
+      const uint64_t t0 = wall_clock64();
+      while (!ready()) {
+        if (__hip_atomic_load(grp.abort_flag, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT)) { ok = 0; break; }
+        if (wall_clock64() - t0 > grp.timeout) {
+          atomicExch(grp.abort_flag, 1);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    // the rows may be cached from an earlier visit of this workgroup
+    if (grp.local) asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory");
+    else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *grp.sflag = ok;
+  }
+  __syncthreads();
+  const int ok = *grp.sflag;
+  __syncthreads();
+  return ok != 0;
+}
+
+// Publishes the visit's row updates, then counts the visit on both blocks.
+__device__ inline void blocks_release(const Group& grp, int* ver, int I, int J) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (!grp.local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    atomicAdd(ver + I, 1);
+    atomicAdd(ver + J, 1);
+  }
 }
 
 }  // namespace nze

@@ -900,6 +900,7 @@ extern "C" int nze_kernel_rowortho(int32_t precision, int32_t R, int32_t C,
   double* dnorm = reinterpret_cast<double*>(scr + 8192);               // R <= 2048 doubles
   int* dperm = reinterpret_cast<int*>(scr + 8192 + 8 * 4 * CHI_LIMIT);   // R ints (row order)
   static_assert(8192 + 12 * 4 * CHI_LIMIT <= HOOK_BYTES, "hook scratch too small");
+  static_assert(256 + 4 * CT_COUNT <= 1024, "hook counters overlap the barrier");
   HIPCHK(hipMemsetAsync(scr, 0, 8192, st));
   Slot s;
   std::memset(&s, 0, sizeof(s));

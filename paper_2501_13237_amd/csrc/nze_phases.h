@@ -521,6 +521,7 @@ __device__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, int C, int g,
   const int nb = (R + BW - 1) / BW;
   const int nbe = nb + (nb & 1);
   const int rounds = nbe - 1, npair = nbe / 2;
+  int* ver = s.ctr + CT_BVER;
   int sweeps = 0;
   bool conv = false;
   for (int sw = 0; sw < s.max_sweeps && sw < MAXSW; ++sw) {
@@ -540,26 +541,32 @@ __device__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, int C, int g,
         s.scal[SC_F2] = f2;
         s.ctr[CT_OFFMAX] = 0;
       }
+      if (sw == 0)
+        for (int b = threadIdx.x; b < nbe; b += NT) ver[b] = 0;
     }
     if (!group_sync(grp)) return false;
     const double F2 = __hip_atomic_load(&s.scal[SC_F2], __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
+    const int base = sw * rounds;
     for (int t = 0; t < rounds; ++t) {
       for (int q = g; q < npair; q += G) {
         const int I = tourney_block(q, t, nbe);
         const int J = tourney_block(nbe - 1 - q, t, nbe);
-        jacobi_pair<T>(s, X, W, R, C, I, J, nb, sw, F2, smem, g == 0, s.perm);
-      }
-      PhaseClock wclk(s.prof != nullptr);
-      if (!group_sync(grp)) return false;
-      if (wclk.on) {
-        const uint64_t now = wall_clock64();
-        if (threadIdx.x == 0) {
-          if (g == 0) s.prof[PF_WAIT] += double(now - wclk.t);
-          atomicAdd(&s.prof[PF_WAIT_ALL], double(now - wclk.t) / G);
+        PhaseClock wclk(s.prof != nullptr);
+        if (!blocks_wait(grp, ver, I, J, base + t)) return false;
+        if (wclk.on) {
+          const uint64_t now = wall_clock64();
+          if (threadIdx.x == 0) {
+            if (g == 0) s.prof[PF_WAIT] += double(now - wclk.t);
+            atomicAdd(&s.prof[PF_WAIT_ALL], double(now - wclk.t) / G);
+          }
         }
+        jacobi_pair<T>(s, X, W, R, C, I, J, nb, sw, F2, smem, g == 0, s.perm);
+        blocks_release(grp, ver, I, J);
       }
     }
+    // every visit of the sweep is complete before the norms are taken
+    if (!group_sync(grp)) return false;
     sweeps = sw + 1;
     const int rot = __hip_atomic_load(&s.ctr[CT_ROT + sw], __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);
