@@ -31,6 +31,41 @@ METRIC = ("MPO two-site updates/s at chi=256 vs plain FP64; extrap. error; "
           "p50/p99 job latency")
 
 
+KERNEL_SOURCES = ["nze_device.h", "nze_phases.h", "nze_mpo.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_layer_traffic_mixed_n50_d24_chi256.md")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2501_13237_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_layer launch from the committed counter summary, or
+    None when the kernel sources changed after the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line and line.split(":", 1)[0].strip() in (
+                "traffic_bytes_per_launch", "kernel_sources_sha256"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def run_job(nze, w, layers, precision, return_mpo=False):
     """One full job; returns (values[L][n_obs], fidelities, stats, layer_ms)."""
     import torch
@@ -300,7 +335,8 @@ def main():
                    "observables": ["Z_25", "X_1 X_2"]},
         "roofline": {"bound": "mfma", "achieved": achieved,
                      "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_TFLOPS["f32"], "traffic": None,
+                     "frac": achieved / PEAK_TFLOPS["f32"],
+                     "traffic": measured_traffic(),
                      "kernel": "k_layer (persistent, one launch per layer)",
                      "mean_layer_ms": float(np.mean(layer_ms)),
                      "algorithmic_tflop_per_step": flops_job / 1e12},

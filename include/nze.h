@@ -208,9 +208,14 @@ int mpo_stats(mpo_t* h, nze_stats* stats, int32_t* bonds);
 int mpo_profile(mpo_t* h, double* ms_out);
 
 /* Schmidt values across bond (l, l+1) of level lv (App. A.1: canonical form
- * at that bond; used for the MPO entanglement entropy).
- *   s_out : capacity cap float64 (host); *count receives the number written.
- * Synchronises; moves the orthogonality centre of level lv only. */
+ * at that bond; used for the MPO entanglement entropy), in decreasing order,
+ * of the state normalised to unit Frobenius norm.  Values at or below
+ * trunc_tol * s_1 are numerical zeros and are not reported.
+ *   s_out : capacity cap float64 (host); the first min(count, cap) values
+ *           are written and *count receives the number of values.
+ * One launch of centre moves (no truncation beyond numerical zeros): the
+ * orthogonality centre of every level of the handle ends at site l + 1.
+ * Synchronises.  NZE_EINVAL for a bad level or bond. */
 int mpo_bond_spectrum(mpo_t* h, int32_t lv, int32_t l, double* s_out,
                       int32_t cap, int32_t* count);
 

@@ -27,7 +27,9 @@ enum { SC_LOG = 0, SC_FID = 1, SC_MAXDISC = 2, SC_MINGAP = 3, SC_F2 = 4,
 // per-MPO int counters
 enum { CT_RANK = 0, CT_ERR = 1, CT_MAXSW = 2, CT_UPD = 3, CT_SWTOT = 4,
        CT_OFFMAX = 5, CT_CAPHIT = 6, CT_ROT = 8, CT_BVER = 8 + MAXSW,
-       CT_COUNT = CT_BVER + 136 };   // CT_BVER: visit counters of <= 136 row blocks
+       CT_WVER = CT_BVER + 136, CT_COUNT = CT_WVER + 136 };
+// CT_BVER / CT_WVER: per row block (<= 136), visits whose data rows / whose
+// accumulator rows are final
 enum { ERR_NOCONV = 1, ERR_NAN = 2, ERR_ABORT = 4 };
 
 // Everything one MPO (one noise level of one job) owns on the device.
@@ -182,7 +184,9 @@ __device__ inline bool group_sync(Group& grp) {
 // Dataflow between the pair visits of a Jacobi sweep: ver[b] counts the
 // visits of row block b.  A visit of round t may start once both of its
 // blocks have completed round t - 1 (ver >= base + t), instead of waiting
-// for every pair of the round.
+// for every pair of the round.  Data rows and accumulator rows have counters
+// of their own, so the accumulator rotation of one visit overlaps the next
+// visits of the same blocks.
 __device__ inline bool blocks_wait(Group& grp, const int* ver, int I, int J,
                                    int target) {
   if (threadIdx.x == 0) {

@@ -566,6 +566,12 @@ extern "C" void mpo_free(mpo_t* h) {
   delete h;
 }
 
+namespace {
+int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& plans,
+                 const int32_t* n_gates, const double* const* ptm,
+                 const std::vector<int>& saved_centre);
+}  // namespace
+
 extern "C" int mpo_apply_layer_batch(mpo_t* const* hs, int32_t k,
                                      const int32_t* n_gates,
                                      const int32_t* const* left_site,
@@ -584,21 +590,43 @@ extern "C" int mpo_apply_layer_batch(mpo_t* const* hs, int32_t k,
   // plans (per handle; every level of a handle follows the same plan)
   std::vector<std::vector<Step>> plans(k);
   std::vector<int> saved_centre(k);
-  size_t nsteps = 0, nmpo = 0, nptm = 0;
   for (int j = 0; j < k; ++j) {
     saved_centre[j] = hs[j]->centre;
     plan_layer(hs[j], n_gates[j], left_site[j], plans[j]);
+  }
+  int rc = launch_plans(hs, k, plans, n_gates, ptm, saved_centre);
+  if (rc == NZE_OK)
+    for (int j = 0; j < k; ++j) hs[j]->layers++;
+  return rc;
+}
+
+namespace {
+
+// One persistent launch running the step lists `plans` (one per handle, all
+// levels of a handle alike) of handles on one stream and precision.  On a
+// failure before the launch the handles' centres are restored.
+int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& plans,
+                 const int32_t* n_gates, const double* const* ptm,
+                 const std::vector<int>& saved_centre) {
+  const int prec = hs[0]->cfg.precision;
+  const hipStream_t stream = hs[0]->stream;
+  size_t nsteps = 0, nmpo = 0, nptm = 0;
+  for (int j = 0; j < k; ++j) {
     nsteps = std::max(nsteps, plans[j].size());
     nmpo += hs[j]->cfg.n_levels;
     nptm += (size_t)hs[j]->cfg.n_levels * n_gates[j];
   }
   if (nsteps == 0) return NZE_OK;
+  auto restore = [&]() { for (int j = 0; j < k; ++j) hs[j]->centre = saved_centre[j]; };
   DevInfo di;
   int rc = dev_info(di);
-  if (rc) return rc;
+  if (rc) { restore(); return rc; }
   const int occ = di.occ[prec == NZE_FP64 ? 0 : 1];
   const int resident = std::max(1, occ * di.cus);
-  if ((int)nmpo > resident) return fail(NZE_EINVAL, "batch has more MPOs than resident workgroups");
+  if ((int)nmpo > resident) {
+    restore();
+    return fail(NZE_EINVAL, "batch has more MPOs than resident workgroups");
+  }
   int chi_cap = 0;
   for (int j = 0; j < k; ++j) chi_cap = std::max(chi_cap, hs[j]->cfg.chi_max);
   const int want = std::max(1, chi_cap / 8);               // pairs per round
@@ -624,7 +652,7 @@ extern "C" int mpo_apply_layer_batch(mpo_t* const* hs, int32_t k,
         bsteps[st * nmpo + mpo0 + l] = s;
       }
     }
-    std::memcpy(bptm + ptm0 * 256, ptm[j], sizeof(double) * 256 * L * ng);
+    if (ng > 0) std::memcpy(bptm + ptm0 * 256, ptm[j], sizeof(double) * 256 * L * ng);
     mpo0 += L;
     ptm0 += (size_t)L * ng;
   }
@@ -650,9 +678,10 @@ extern "C" int mpo_apply_layer_batch(mpo_t* const* hs, int32_t k,
   const void* fn = prec == NZE_FP64 ? reinterpret_cast<const void*>(&k_layer<double>)
                                     : reinterpret_cast<const void*>(&k_layer<float>);
   HIPCHK(hipLaunchCooperativeKernel(fn, dim3((unsigned)(nmpo * G)), dim3(NT), args, 0, stream));
-  for (int j = 0; j < k; ++j) hs[j]->layers++;
   return NZE_OK;
 }
+
+}  // namespace
 
 extern "C" int mpo_apply_layer(mpo_t* h, int32_t n_gates,
                                const int32_t* left_site, const double* ptm) {
@@ -777,8 +806,34 @@ extern "C" int mpo_profile(mpo_t* h, double* ms_out) {
 
 extern "C" int mpo_bond_spectrum(mpo_t* h, int32_t lv, int32_t l, double* s_out,
                                  int32_t cap, int32_t* count) {
-  (void)h; (void)lv; (void)l; (void)s_out; (void)cap; (void)count;
-  return fail(NZE_EINVAL, "mpo_bond_spectrum is not available in this build");
+  if (!h) return fail(NZE_EINVAL, "NULL handle");
+  const int n = h->cfg.n;
+  if (lv < 0 || lv >= h->cfg.n_levels || l < 0 || l + 1 >= n || !s_out || cap < 1 || !count)
+    return fail(NZE_EINVAL, "bad bond spectrum arguments");
+  int rc = read_errors(h);
+  if (rc) return rc;
+  // centre to l, then one more left-to-right move: its SVD is the bond's
+  std::vector<std::vector<Step>> plans(1);
+  std::vector<int> saved_centre{h->centre};
+  while (h->centre < l) { plans[0].push_back({OP_MOVE_LR, h->centre, 0, 0}); h->centre++; }
+  while (h->centre > l) { plans[0].push_back({OP_MOVE_RL, h->centre, 0, 0}); h->centre--; }
+  plans[0].push_back({OP_MOVE_LR, l, 0, 0});
+  h->centre = l + 1;
+  const int32_t ng = 0;
+  const double* no_ptm = nullptr;
+  rc = launch_plans(&h, 1, plans, &ng, &no_ptm, saved_centre);
+  if (rc) return rc;
+  rc = read_errors(h);
+  if (rc) return rc;
+  int r = 0;
+  const Slot& s = h->slots[lv];
+  HIPCHK(hipMemcpyAsync(&r, s.ctr + CT_RANK, 4, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  const int m = std::min(r, (int)cap);
+  HIPCHK(hipMemcpyAsync(s_out, s.sval, (size_t)m * 8, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  *count = r;
+  return NZE_OK;
 }
 
 // ------------------------------------------------------ kernel-level hooks
@@ -896,11 +951,11 @@ extern "C" int nze_kernel_rowortho(int32_t precision, int32_t R, int32_t C,
   if (rc) return rc;
   double* dscal = reinterpret_cast<double*>(scr);
   int* dctr = reinterpret_cast<int*>(scr + 256);
-  int* dbar = reinterpret_cast<int*>(scr + 1024);
+  int* dbar = reinterpret_cast<int*>(scr + 2048);
   double* dnorm = reinterpret_cast<double*>(scr + 8192);               // R <= 2048 doubles
   int* dperm = reinterpret_cast<int*>(scr + 8192 + 8 * 4 * CHI_LIMIT);   // R ints (row order)
   static_assert(8192 + 12 * 4 * CHI_LIMIT <= HOOK_BYTES, "hook scratch too small");
-  static_assert(256 + 4 * CT_COUNT <= 1024, "hook counters overlap the barrier");
+  static_assert(256 + 4 * CT_COUNT <= 2048, "hook counters overlap the barrier");
   HIPCHK(hipMemsetAsync(scr, 0, 8192, st));
   Slot s;
   std::memset(&s, 0, sizeof(s));

@@ -414,9 +414,10 @@ __device__ void pair_rotate(T* M, int ld, int ncols, const PairLds& L) {
 
 // One pair step of sweep `sw`: Gram, convergence test, inner solve, rotate.
 template <typename T>
-__device__ void jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
+__device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
                             int J, int nb, int sw, double F2, double* smem,
-                            bool timed, const int* order) {
+                            bool timed, const int* order, Group& grp,
+                            int* verX, int* verW, int target) {
   const PairLds L = pair_lds(smem);
   const int tid = threadIdx.x;
   PhaseClock clk(timed && s.prof != nullptr);
@@ -454,16 +455,21 @@ __device__ void jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
   const int go = L.flag[1];
   __syncthreads();
   clk.lap(s.prof, PF_CHECK);
-  if (!go) return;
-  if (tid == 0) atomicAdd(&s.ctr[CT_ROT + sw], 1);
-  const int nsw = inner_eigh(L, INNER_SWEEPS);
-  clk.lap(s.prof, PF_EIGH);
-  if (clk.on && tid == 0) { s.prof[PF_EIGH_SW] += nsw; s.prof[PF_PAIRS] += 1.0; }
-  pair_rotate<T>(X, C, C, L);
-  clk.lap(s.prof, PF_ROTX);
-  pair_rotate<T>(W, R, R, L);
-  __syncthreads();
+  if (go) {
+    if (tid == 0) atomicAdd(&s.ctr[CT_ROT + sw], 1);
+    const int nsw = inner_eigh(L, INNER_SWEEPS);
+    clk.lap(s.prof, PF_EIGH);
+    if (clk.on && tid == 0) { s.prof[PF_EIGH_SW] += nsw; s.prof[PF_PAIRS] += 1.0; }
+    pair_rotate<T>(X, C, C, L);
+    clk.lap(s.prof, PF_ROTX);
+  }
+  blocks_release(grp, verX, I, J);
+  // accumulator rows: previous visits of both blocks first, in visit order
+  if (!blocks_wait(grp, verW, I, J, target)) return false;
+  if (go) pair_rotate<T>(W, R, R, L);
+  blocks_release(grp, verW, I, J);
   clk.lap(s.prof, PF_ROTW);
+  return true;
 }
 
 // squared row norms in float64
@@ -522,6 +528,7 @@ __device__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, int C, int g,
   const int nbe = nb + (nb & 1);
   const int rounds = nbe - 1, npair = nbe / 2;
   int* ver = s.ctr + CT_BVER;
+  int* wver = s.ctr + CT_WVER;
   int sweeps = 0;
   bool conv = false;
   for (int sw = 0; sw < s.max_sweeps && sw < MAXSW; ++sw) {
@@ -542,7 +549,7 @@ __device__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, int C, int g,
         s.ctr[CT_OFFMAX] = 0;
       }
       if (sw == 0)
-        for (int b = threadIdx.x; b < nbe; b += NT) ver[b] = 0;
+        for (int b = threadIdx.x; b < nbe; b += NT) { ver[b] = 0; wver[b] = 0; }
     }
     if (!group_sync(grp)) return false;
     const double F2 = __hip_atomic_load(&s.scal[SC_F2], __ATOMIC_RELAXED,
@@ -561,8 +568,9 @@ __device__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, int C, int g,
             atomicAdd(&s.prof[PF_WAIT_ALL], double(now - wclk.t) / G);
           }
         }
-        jacobi_pair<T>(s, X, W, R, C, I, J, nb, sw, F2, smem, g == 0, s.perm);
-        blocks_release(grp, ver, I, J);
+        if (!jacobi_pair<T>(s, X, W, R, C, I, J, nb, sw, F2, smem, g == 0, s.perm,
+                            grp, ver, wver, base + t))
+          return false;
       }
     }
     // every visit of the sweep is complete before the norms are taken

@@ -336,6 +336,22 @@ class MPO:
                      cap_hits=s.cap_hits, cap_offdiag=s.cap_offdiag)
                 for s in st], bonds
 
+    def bond_spectrum(self, level, bond):
+        """Schmidt values across bond (bond, bond + 1) of one level."""
+        cap = 4 * self.chi
+        out = np.zeros(cap)
+        cnt = ctypes.c_int32()
+        _check(lib().mpo_bond_spectrum(self.h, level, bond, _dp(out), cap,
+                                       ctypes.byref(cnt)))
+        return out[:min(cnt.value, cap)].copy()
+
+    def entanglement_entropy(self, level, bond):
+        """MPO entanglement entropy -sum p ln p, p = s^2 / sum s^2 (App. A.1)."""
+        s = self.bond_spectrum(level, bond)
+        p = s * s / np.sum(s * s)
+        p = p[p > 0]
+        return float(-np.sum(p * np.log(p)))
+
     PROFILE_NAMES = ["theta", "gram", "check", "eigh", "rot_x", "rot_w",
                      "jacobi_wait", "norms", "select", "absorb", "move_prep",
                      "move_absorb", "inner_sweeps", "pair_solves", "wait_mean",

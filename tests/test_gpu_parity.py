@@ -183,6 +183,38 @@ def test_xcd_groups_match_device_groups_bitwise(precision):
         assert np.array_equal(v8[j], v1[0]) and f8[j] == f1[0] and t8[j] == t1[0]
 
 
+@pytest.mark.parametrize("precision,tol", [(nze.NZE_FP64, FP64_TOL),
+                                           (nze.NZE_MIXED, MIXED_TOL)])
+def test_bond_spectra_and_entropy(precision, tol):
+    # Schmidt values at every bond (canonical form there) and the MPO
+    # entanglement entropy, exact (n = 8, chi = 256) and truncated
+    # (n = 10, chi = 24) runs, against the oracle's LAPACK spectra
+    for n, chi, depth, seed in ((8, 256, 8, 41), (10, 24, 8, 42)):
+        layers = workloads.brickwork(n, depth, seed=seed)
+        noise = {"dep": 2e-3}
+        factors = [1.0, 4.0]
+        _say(f"bond spectra n={n} chi={chi} prec={precision}")
+        g = _gpu_run(n, layers, noise, factors, chi, precision)
+        orc = _oracle_run(n, layers, noise, factors, chi,
+                          tie=(1e-10 if precision == nze.NZE_FP64 else 1e-5))
+        for j, m in enumerate(orc):
+            for b in range(n - 1):
+                sg = g.bond_spectrum(j, b)
+                so = m.bond_spectrum(b)
+                so = so / np.linalg.norm(so)
+                k = min(sg.size, so.size)
+                assert sg.size >= 1 and abs(np.linalg.norm(sg) - 1.0) < 10 * tol
+                assert np.max(np.abs(sg[:k] - so[:k])) < tol
+                # values the GPU does not report are numerical zeros
+                assert so.size <= k or so[k] < 1e3 * tol
+                assert abs(g.entanglement_entropy(j, b) - m.entanglement_entropy(b)) < 100 * tol
+        # the moves change the gauge only: readout is unchanged
+        obs = workloads.z_singles(n)
+        vals, fid, _ = g.expect(obs)
+        for j, m in enumerate(orc):
+            assert np.max(np.abs(vals[j] - m.expectations(obs))) < tol
+
+
 def test_invalid_layer_rejected():
     m = nze.MPO(6, 8, 1, nze.NZE_FP64)
     with pytest.raises(nze.NzeError) as e:
