@@ -258,6 +258,8 @@ def main():
                     help="also run the serving loop on this many jobs")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-sustainable-rate", type=float, default=0.0)
+    ap.add_argument("--no-extrapolation-error", action="store_true",
+                    help="skip the n=8 extrapolation-error leg (profiling runs)")
     ap.add_argument("--skip-main", action="store_true",
                     help="only the serving runs")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -358,7 +360,8 @@ def main():
         out["speedup_mixed_vs_fp64"] = value / v64
         out["mixed_vs_fp64_max_abs_obs"] = float(np.max(np.abs(vals - vals64)))
         out["mixed_vs_fp64_max_rel_fid"] = float(np.max(np.abs(fid - fid64) / fid64))
-    out["extrapolation_error_n8"] = extrapolation_error(nze, workloads)
+    if not args.no_extrapolation_error:
+        out["extrapolation_error_n8"] = extrapolation_error(nze, workloads)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, layers)
     print(json.dumps(out), flush=True)
