@@ -83,16 +83,12 @@ __global__ __launch_bounds__(NT) void k_layer(const Slot* slots,
     bool ok = true;
     switch (op.op) {
       case OP_GATE_LR:
-        ok = op_gate<T>(s, op.k, true, ptms + (size_t)op.ptm * 256, g, G, grp, smem);
-        break;
       case OP_GATE_RL:
-        ok = op_gate<T>(s, op.k, false, ptms + (size_t)op.ptm * 256, g, G, grp, smem);
+        ok = op_gate<T>(s, op.k, op.op == OP_GATE_LR, ptms + (size_t)op.ptm * 256, g, G, grp, smem);
         break;
       case OP_MOVE_LR:
-        ok = op_move<T>(s, op.k, true, g, G, grp, smem);
-        break;
       case OP_MOVE_RL:
-        ok = op_move<T>(s, op.k, false, g, G, grp, smem);
+        ok = op_move<T>(s, op.k, op.op == OP_MOVE_LR, g, G, grp, smem);
         break;
       default:
         break;

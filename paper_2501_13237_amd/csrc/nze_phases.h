@@ -264,9 +264,9 @@ __device__ void pair_gram(const T* X, int ld, int C, const PairLds& L) {
   __syncthreads();
 }
 
-// Reciprocal and reciprocal square root: hardware seeds (v_rcp_f64,
-// v_rsq_f64) refined by two Newton-Raphson steps, x_{k+1} = x_k (2 - a x_k)
-// and y_{k+1} = y_k (3 - a y_k^2) / 2; each step squares the relative error.
+// Reciprocal square root: hardware seed (v_rsq_f64) refined by two
+// Newton-Raphson steps y_{k+1} = y_k (3 - a y_k^2) / 2, each of which squares
+// the relative error.
 __device__ inline double nr_rsq(double a) {
   double y = __builtin_amdgcn_rsq(a);
   y = y * fma(-0.5 * a * y, y, 1.5);
@@ -278,23 +278,29 @@ __device__ inline double nr_rsq(double a) {
 // [[g_pp, g_pq], [g_pq, g_qq]] (J = [[c, s], [-s, c]], J^T G J diagonal):
 // tau = (g_qq - g_pp) / (2 g_pq), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
 // c = 1 / sqrt(1 + t^2), s = t c.  Identity below the threshold.
-__device__ inline void jacobi_cs(double gpp, double gqq, double gpq,
-                                 double floor_abs, double& c, double& sn) {
-  c = 1.0;
-  sn = 0.0;
-  const double a2 = gpq * gpq;
-  if (fabs(gpq) > floor_abs && a2 > 1e-30 * fabs(gpp * gqq)) {
-    // t = tan(theta) only sets how much of g_pq the rotation removes: the
-    // hardware reciprocal and root (about 1e-7 relative) leave ~1e-7 g_pq,
-    // which the next visit removes.  c must make (c, t c) orthonormal to
-    // rounding, so its root is Newton-refined.
-    const double tau = (gqq - gpp) * __builtin_amdgcn_rcp(2.0 * gpq);
-    const double u = fma(tau, tau, 1.0);
-    const double t = (tau >= 0 ? 1.0 : -1.0) *
-                     __builtin_amdgcn_rcp(fabs(tau) + u * __builtin_amdgcn_rsq(u));
-    c = nr_rsq(fma(t, t, 1.0));
-    sn = t * c;
-  }
+// t only sets how much of g_pq the rotation removes: the unrefined hardware
+// reciprocal and root (about 1e-7 relative) leave ~1e-7 g_pq for the next
+// visit.  c must make (c, t c) orthonormal to rounding, so its root is
+// refined.  Two pivots are computed at once, without branches, so that the
+// two dependent chains of reciprocals and roots interleave.
+__device__ inline void jacobi_cs2(double gpp, double gqq, double gpq,
+                                  double hpp, double hqq, double hpq,
+                                  double floor_abs, double& c, double& sn,
+                                  double& c2, double& s2) {
+  const bool ra = fabs(gpq) > floor_abs && gpq * gpq > 1e-30 * fabs(gpp * gqq);
+  const bool rb = fabs(hpq) > floor_abs && hpq * hpq > 1e-30 * fabs(hpp * hqq);
+  const double ta = (gqq - gpp) * __builtin_amdgcn_rcp(2.0 * (ra ? gpq : 1.0));
+  const double tb = (hqq - hpp) * __builtin_amdgcn_rcp(2.0 * (rb ? hpq : 1.0));
+  const double ua = fma(ta, ta, 1.0), ub = fma(tb, tb, 1.0);
+  const double xa = (ta >= 0 ? 1.0 : -1.0) *
+                    __builtin_amdgcn_rcp(fabs(ta) + ua * __builtin_amdgcn_rsq(ua));
+  const double xb = (tb >= 0 ? 1.0 : -1.0) *
+                    __builtin_amdgcn_rcp(fabs(tb) + ub * __builtin_amdgcn_rsq(ub));
+  const double ca = nr_rsq(fma(xa, xa, 1.0)), cb = nr_rsq(fma(xb, xb, 1.0));
+  c = ra ? ca : 1.0;
+  sn = ra ? xa * ca : 0.0;
+  c2 = rb ? cb : 1.0;
+  s2 = rb ? xb * cb : 0.0;
 }
 
 // Round-robin pairing of 32 indices: pair k (0..15) of step st.
@@ -339,9 +345,7 @@ __device__ int inner_eigh(const PairLds& L, int max_inner) {
       const double qa = L.Qs[u0 * GLD + p2], qb = L.Qs[u0 * GLD + q2];
       const double qc = L.Qs[(u0 + 1) * GLD + p2], qd = L.Qs[(u0 + 1) * GLD + q2];
       double c, sn, c2, s2;
-      jacobi_cs(gpp, gqq, gpq, floor_abs, c, sn);
-      if (P2 == P) { c2 = c; s2 = sn; }
-      else jacobi_cs(hpp, hqq, hpq, floor_abs, c2, s2);
+      jacobi_cs2(gpp, gqq, gpq, hpp, hqq, hpq, floor_abs, c, sn, c2, s2);
       any |= (sn != 0.0);
       const double h11 = c * g11 - sn * g21, h12 = c * g12 - sn * g22;
       const double h21 = sn * g11 + c * g21, h22 = sn * g12 + c * g22;
@@ -522,7 +526,7 @@ __device__ inline int tourney_block(int pos, int t, int nbe) {
 }
 
 template <typename T>
-__device__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, int C, int g,
+__device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, int C, int g,
                              int G, Group& grp, double* smem) {
   const int nb = (R + BW - 1) / BW;
   const int nbe = nb + (nb & 1);
@@ -668,7 +672,7 @@ __device__ void phase_select(const Slot& s, int R, bool gate, double* smem) {
 // ----------------------------------------------------------- full ops
 
 template <typename T>
-__device__ bool op_gate(const Slot& s, int k, bool ltr, const double* R, int g,
+__device__ __forceinline__ bool op_gate(const Slot& s, int k, bool ltr, const double* R, int g,
                         int G, Group& grp, double* smem) {
   const int cl = s.dims[k], cr = s.dims[k + 2];
   const int Rr = ltr ? 4 * cl : 4 * cr, Cc = ltr ? 4 * cr : 4 * cl;
@@ -706,7 +710,7 @@ __device__ bool op_gate(const Slot& s, int k, bool ltr, const double* R, int g,
 
 // Centre move away from site c: to c+1 (ltr) or c-1.
 template <typename T>
-__device__ bool op_move(const Slot& s, int c, bool ltr, int g, int G,
+__device__ __forceinline__ bool op_move(const Slot& s, int c, bool ltr, int g, int G,
                         Group& grp, double* smem) {
   const int cl = s.dims[c], cr = s.dims[c + 1];
   T* X = reinterpret_cast<T*>(s.X);
