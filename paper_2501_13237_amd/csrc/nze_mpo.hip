@@ -33,15 +33,13 @@ __device__ inline int ld_agent(const int* p) {
 //             the XCD's L2.
 // bar: [nmpo] group counters, then 8 per-XCD tickets and the census counter.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_layer(const Slot* slots,
+__device__ __forceinline__ void layer_body(const Slot* slots,
                                              const Step* steps,
                                              const double* ptms, int nsteps,
                                              int nmpo, int G, int* bar,
                                              int* abort_flag,
                                              unsigned long long timeout,
-                                             int xcd) {
-  __shared__ double smem[SMEM_DOUBLES];
-  __shared__ int sflag[4];
+                                             int xcd, double* smem, int* sflag) {
   int mpo = blockIdx.x % nmpo;
   int g = blockIdx.x / nmpo;
   if (xcd) {
@@ -99,6 +97,26 @@ __global__ __launch_bounds__(NT) void k_layer(const Slot* slots,
     }
   }
 }
+
+// Entry points.  The float kernel is built for two workgroups per CU (at most
+// 256 registers a lane), which doubles the MPOs one launch can hold when
+// serving; the double kernel needs more registers and runs one per CU.
+#define NZE_LAYER_ARGS const Slot* slots, const Step* steps, const double* ptms, \
+    int nsteps, int nmpo, int G, int* bar, int* abort_flag,                    \
+    unsigned long long timeout, int xcd
+__global__ __launch_bounds__(NT, 2) void k_layer_f32(NZE_LAYER_ARGS) {
+  __shared__ double smem[SMEM_DOUBLES];
+  __shared__ int sflag[4];
+  layer_body<float>(slots, steps, ptms, nsteps, nmpo, G, bar, abort_flag, timeout,
+                    xcd, smem, sflag);
+}
+__global__ __launch_bounds__(NT) void k_layer_f64(NZE_LAYER_ARGS) {
+  __shared__ double smem[SMEM_DOUBLES];
+  __shared__ int sflag[4];
+  layer_body<double>(slots, steps, ptms, nsteps, nmpo, G, bar, abort_flag, timeout,
+                     xcd, smem, sflag);
+}
+#undef NZE_LAYER_ARGS
 
 __global__ void k_fill_int(int* p, int n, int v) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -362,9 +380,9 @@ int dev_info(DevInfo& out) {
   DevInfo di;
   HIPCHK(hipDeviceGetAttribute(&di.cus, hipDeviceAttributeMultiprocessorCount, dev));
   int occ = 0;
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_layer<double>, NT, 0));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_layer_f64, NT, 0));
   di.occ[0] = occ;
-  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_layer<float>, NT, 0));
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_layer_f32, NT, 0));
   di.occ[1] = occ;
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
@@ -625,7 +643,10 @@ int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& 
   }
   int chi_cap = 0;
   for (int j = 0; j < k; ++j) chi_cap = std::max(chi_cap, hs[j]->cfg.chi_max);
-  const int want = std::max(1, chi_cap / 8);               // pairs per round
+  // pairs per round (m / 32 at the largest bond): a pair visit waits for the
+  // previous round's visits of its blocks, so more workgroups than pairs do
+  // not shorten the chain of rounds (measured)
+  const int want = std::max(1, chi_cap / 8);
   const int G = std::max(1, std::min(want, resident / (int)nmpo));
   // blob: slots | steps | ptms | bar + abort
   const size_t off_steps = align_up(sizeof(Slot) * nmpo);
@@ -671,8 +692,8 @@ int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& 
   // nmpo * G workgroups is spread evenly over the 8 XCDs)
   int a_xcd = (di.xcd_local && nmpo % 8 == 0) ? 1 : 0;
   void* args[] = {&a_slots, &a_steps, &a_ptm, &a_nsteps, &a_nmpo, &a_G, &a_bar, &a_abort, &a_to, &a_xcd};
-  const void* fn = prec == NZE_FP64 ? reinterpret_cast<const void*>(&k_layer<double>)
-                                    : reinterpret_cast<const void*>(&k_layer<float>);
+  const void* fn = prec == NZE_FP64 ? reinterpret_cast<const void*>(&k_layer_f64)
+                                    : reinterpret_cast<const void*>(&k_layer_f32);
   HIPCHK(hipLaunchCooperativeKernel(fn, dim3((unsigned)(nmpo * G)), dim3(NT), args, 0, stream));
   return NZE_OK;
 }

@@ -558,9 +558,14 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
     if (!group_sync(grp)) return false;
     const double F2 = __hip_atomic_load(&s.scal[SC_F2], __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
+    // visit v = t npair + q (pair q of round t) belongs to workgroup v mod G;
+    // each workgroup takes its visits in increasing order, and a visit waits
+    // only for the previous round's visits of its two blocks, so rounds
+    // overlap when G exceeds the pairs per round
     const int base = sw * rounds;
-    for (int t = 0; t < rounds; ++t) {
-      for (int q = g; q < npair; q += G) {
+    for (int v = g; v < rounds * npair; v += G) {
+      const int t = v / npair, q = v - t * npair;
+      {
         const int I = tourney_block(q, t, nbe);
         const int J = tourney_block(nbe - 1 - q, t, nbe);
         PhaseClock wclk(s.prof != nullptr);
