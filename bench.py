@@ -185,6 +185,8 @@ def serve_run(nze, jobs, rate, seed, precision):
             if st == 2:
                 lat[k] = (time.perf_counter() - t0) - arrivals[k]
                 done_upd += jobs[k]["updates"]
+                print(f"serve: job {k} done after {lat[k]:.2f} s "
+                      f"({len(lat)}/{len(jobs)})", file=sys.stderr, flush=True)
             elif st < 0:
                 raise RuntimeError(f"job {k} failed with {st}")
     wall = time.perf_counter() - t0

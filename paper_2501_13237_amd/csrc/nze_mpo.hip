@@ -24,8 +24,9 @@ __device__ inline int ld_agent(const int* p) {
 
 // One launch applies a whole layer: every MPO of the batch walks through its
 // list of steps (centre moves and gates) with a group of workgroups.
-//   xcd == 0: workgroup b serves MPO b % nmpo with G per MPO, device-scope
-//             group barriers.
+//   xcd == 0: workgroup b serves MPO wgmap[2b] as member wgmap[2b + 1] of a
+//             group of gsize[MPO] (sized by the host to the MPO's work),
+//             device-scope group barriers.
 //   xcd == 1 (nmpo a multiple of 8): MPO m is served by workgroups running on
 //             XCD m % 8, identified by the hardware XCC_ID and numbered by
 //             arrival; after one census of the whole grid each XCD splits its
@@ -39,10 +40,15 @@ __device__ __forceinline__ void layer_body(const Slot* slots,
                                              int nmpo, int G, int* bar,
                                              int* abort_flag,
                                              unsigned long long timeout,
-                                             int xcd, double* smem, int* sflag) {
-  int mpo = blockIdx.x % nmpo;
-  int g = blockIdx.x / nmpo;
-  if (xcd) {
+                                             int xcd, const int* wgmap,
+                                             const int* gsize, double* smem,
+                                             int* sflag) {
+  int mpo = 0, g = 0;
+  if (!xcd) {
+    mpo = wgmap[2 * blockIdx.x];
+    g = wgmap[2 * blockIdx.x + 1];
+    G = gsize[mpo];
+  } else {
     int* tick = bar + nmpo;
     int* census = bar + nmpo + 8;
     if (threadIdx.x == 0) {
@@ -103,18 +109,18 @@ __device__ __forceinline__ void layer_body(const Slot* slots,
 // serving; the double kernel needs more registers and runs one per CU.
 #define NZE_LAYER_ARGS const Slot* slots, const Step* steps, const double* ptms, \
     int nsteps, int nmpo, int G, int* bar, int* abort_flag,                    \
-    unsigned long long timeout, int xcd
+    unsigned long long timeout, int xcd, const int* wgmap, const int* gsize
 __global__ __launch_bounds__(NT, 2) void k_layer_f32(NZE_LAYER_ARGS) {
   __shared__ double smem[SMEM_DOUBLES];
   __shared__ int sflag[4];
   layer_body<float>(slots, steps, ptms, nsteps, nmpo, G, bar, abort_flag, timeout,
-                    xcd, smem, sflag);
+                    xcd, wgmap, gsize, smem, sflag);
 }
 __global__ __launch_bounds__(NT) void k_layer_f64(NZE_LAYER_ARGS) {
   __shared__ double smem[SMEM_DOUBLES];
   __shared__ int sflag[4];
   layer_body<double>(slots, steps, ptms, nsteps, nmpo, G, bar, abort_flag, timeout,
-                     xcd, smem, sflag);
+                     xcd, wgmap, gsize, smem, sflag);
 }
 #undef NZE_LAYER_ARGS
 
@@ -641,19 +647,54 @@ int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& 
     restore();
     return fail(NZE_EINVAL, "batch has more MPOs than resident workgroups");
   }
-  int chi_cap = 0;
-  for (int j = 0; j < k; ++j) chi_cap = std::max(chi_cap, hs[j]->cfg.chi_max);
-  // pairs per round (m / 32 at the largest bond): a pair visit waits for the
-  // previous round's visits of its blocks, so more workgroups than pairs do
-  // not shorten the chain of rounds (measured)
-  const int want = std::max(1, chi_cap / 8);
-  const int G = std::max(1, std::min(want, resident / (int)nmpo));
-  // blob: slots | steps | ptms | bar + abort
+  // Group size of each MPO: the pairs per Jacobi round at its chi cap
+  // (m / 32; a pair visit waits for the previous round's visits of its
+  // blocks, so more workgroups than pairs do not shorten the chain of rounds,
+  // measured).  When the batch asks for more than the resident workgroups,
+  // every request is scaled down alike, so that MPOs of different widths keep
+  // their relative shares.
+  std::vector<int> gm(nmpo);
+  {
+    size_t m = 0;
+    for (int j = 0; j < k; ++j)
+      for (int l = 0; l < hs[j]->cfg.n_levels; ++l) gm[m++] = std::max(1, hs[j]->cfg.chi_max / 8);
+  }
+  long long want_tot = 0;
+  for (int x : gm) want_tot += x;
+  if (want_tot > resident) {
+    const double scale = double(resident) / double(want_tot);
+    want_tot = 0;
+    for (int& x : gm) { x = std::max(1, (int)(x * scale)); want_tot += x; }
+    while (want_tot > resident) {            // the max(1, .) clamps can overshoot
+      auto it = std::max_element(gm.begin(), gm.end());
+      if (*it <= 1) break;
+      --*it;
+      --want_tot;
+    }
+  }
+  const bool uniform = std::all_of(gm.begin(), gm.end(), [&](int x) { return x == gm[0]; });
+  const int G = gm[0];
+  // XCD-local groups: every XCD hosts nmpo / 8 whole MPOs (the grid of
+  // nmpo * G workgroups is spread evenly over the 8 XCDs)
+  int a_xcd = (di.xcd_local && nmpo % 8 == 0 && uniform) ? 1 : 0;
+  const int grid = a_xcd ? (int)nmpo * G : (int)want_tot;
+  // blob: slots | steps | ptms | bar + abort | workgroup map | group sizes
   const size_t off_steps = align_up(sizeof(Slot) * nmpo);
   const size_t off_ptm = off_steps + align_up(sizeof(Step) * nsteps * nmpo);
   const size_t off_bar = off_ptm + align_up(8 * 256 * std::max<size_t>(nptm, 1));
-  const size_t total = off_bar + align_up(4 * (nmpo + 10));
+  const size_t off_map = off_bar + align_up(4 * (nmpo + 10));
+  const size_t off_gsz = off_map + align_up(8 * (size_t)grid);
+  const size_t total = off_gsz + align_up(4 * nmpo);
   std::vector<char> blob(total, 0);
+  {
+    int* map = reinterpret_cast<int*>(blob.data() + off_map);
+    int* gsz = reinterpret_cast<int*>(blob.data() + off_gsz);
+    int b = 0;
+    for (size_t m = 0; m < nmpo; ++m) {
+      gsz[m] = gm[m];
+      for (int g = 0; g < gm[m] && !a_xcd; ++g, ++b) { map[2 * b] = (int)m; map[2 * b + 1] = g; }
+    }
+  }
   Slot* bslots = reinterpret_cast<Slot*>(blob.data());
   Step* bsteps = reinterpret_cast<Step*>(blob.data() + off_steps);
   double* bptm = reinterpret_cast<double*>(blob.data() + off_ptm);
@@ -688,13 +729,13 @@ int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& 
   int* a_bar = dbar;                 // nmpo group counters, 8 tickets, census
   int* a_abort = dbar + nmpo + 9;
   unsigned long long a_to = di.timeout_ticks;
-  // XCD-local groups: every XCD hosts nmpo / 8 whole MPOs (the grid of
-  // nmpo * G workgroups is spread evenly over the 8 XCDs)
-  int a_xcd = (di.xcd_local && nmpo % 8 == 0) ? 1 : 0;
-  void* args[] = {&a_slots, &a_steps, &a_ptm, &a_nsteps, &a_nmpo, &a_G, &a_bar, &a_abort, &a_to, &a_xcd};
+  const int* a_map = reinterpret_cast<const int*>(dev + off_map);
+  const int* a_gsz = reinterpret_cast<const int*>(dev + off_gsz);
+  void* args[] = {&a_slots, &a_steps, &a_ptm, &a_nsteps, &a_nmpo, &a_G, &a_bar, &a_abort,
+                  &a_to, &a_xcd, &a_map, &a_gsz};
   const void* fn = prec == NZE_FP64 ? reinterpret_cast<const void*>(&k_layer_f64)
                                     : reinterpret_cast<const void*>(&k_layer_f32);
-  HIPCHK(hipLaunchCooperativeKernel(fn, dim3((unsigned)(nmpo * G)), dim3(NT), args, 0, stream));
+  HIPCHK(hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(NT), args, 0, stream));
   return NZE_OK;
 }
 

@@ -142,7 +142,7 @@ extern "C" int nze_server_submit(nze_server_t* s, const nze_job_spec* spec,
 
 namespace {
 
-constexpr int MAX_LAUNCH_MPOS = 128;
+constexpr int MAX_LAUNCH_MPOS = 256;   // resident workgroups of the double kernel
 
 int levels_of(nze_server* s, mpo_t* h) {
   for (Job* j : s->active)
