@@ -103,7 +103,7 @@ typedef struct mpo_config {
                           (C = row length);
                           0 -> 1e-13 (FP64) / 2e-6 (mixed);
                           tol_abs is 1e-15 (FP64) / 1e-6 (mixed)             */
-  int32_t max_sweeps;  /* Jacobi sweep cap (<= 40); 0 -> 30                   */
+  int32_t max_sweeps;  /* Jacobi sweep cap (<= 40); 0 -> 40                   */
   int32_t block;       /* Jacobi row-block width b (pairs are 2b rows);
                           0 -> chosen by the built-in tuner                   */
 } mpo_config;
@@ -327,11 +327,13 @@ int nze_server_stats(nze_server_t* s, size_t* arena_high_water, int64_t* launche
  * or its transpose when ltr == 0.  1 <= cl, cm, cr <= 512.
  *
  * nze_kernel_rowortho: block one-sided Jacobi on the rows of X (R x C, C a
- * multiple of 4) with the rotations accumulated into W (R x R, overwritten,
- * starts as the identity): on return W X has mutually orthogonal rows and
- * W X = (W) X_in.  norms receives the R squared row norms of the result
- * (host, float64).  *sweeps gets the sweeps used (NULL ok).  Returns
- * NZE_ENOCONV if max_sweeps were not enough.  1 <= R <= 2048. */
+ * multiple of 4, row-major, in place) with the rotations accumulated into W
+ * (R x R, overwritten; it starts as the identity): on return X holds
+ * W X_in, whose rows are mutually orthogonal (their norms are the singular
+ * values of X_in, in no particular order), and W is orthogonal.  norms
+ * receives the R squared row norms of the result (host, float64).  *sweeps
+ * gets the sweeps used (NULL ok).  Returns NZE_ENOCONV if max_sweeps were not
+ * enough.  1 <= R <= 2048. */
 int nze_kernel_theta(int32_t precision, int32_t cl, int32_t cm, int32_t cr,
                      const void* A, const void* B, const double* ptm,
                      int32_t ltr, void* X, void* stream);

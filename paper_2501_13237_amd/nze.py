@@ -247,7 +247,7 @@ def kernel_theta(A, B, ptm16, ltr=True):
     return X
 
 
-def kernel_rowortho(X, tol_rel, tol_abs, max_sweeps=30):
+def kernel_rowortho(X, tol_rel, tol_abs, max_sweeps=40):
     """Block one-sided Jacobi on the rows of the device matrix X (in place);
     returns (W, squared row norms, sweeps)."""
     import torch

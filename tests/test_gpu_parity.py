@@ -215,6 +215,109 @@ def test_bond_spectra_and_entropy(precision, tol):
             assert np.max(np.abs(vals[j] - m.expectations(obs))) < tol
 
 
+def _torch_dev(a, precision):
+    import torch
+    dt = torch.float64 if precision == nze.NZE_FP64 else torch.float32
+    return torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda")
+
+
+@pytest.mark.parametrize("precision", [nze.NZE_FP64, nze.NZE_MIXED])
+@pytest.mark.parametrize("dims", [(256, 256, 256), (37, 50, 29), (1, 4, 16)])
+def test_kernel_theta_against_oracle(precision, dims):
+    # one two-site contraction with the noisy-gate superoperator, at the
+    # saturated chi = 256 of the n = 50 workload and at ragged shapes, both
+    # orientations, against the oracle's Theta'
+    cl, cm, cr = dims
+    rng = np.random.default_rng(100 + cl)
+    A = rng.standard_normal((cl, 4, cm)) / np.sqrt(4 * cm)
+    B = rng.standard_normal((cm, 4, cr)) / np.sqrt(cm)
+    U = workloads.haar_su4(rng)
+    R = ptm.ptm_noisy_gate(U, ptm.Noise(dep=1e-3, ad=5e-4))
+    m = ompo.PauliMPO(2, 1)
+    m.sites = [A, B]
+    ref = m.two_site_block(0, R)
+    tol = 1e-12 if precision == nze.NZE_FP64 else 1e-5
+    for ltr in (True, False):
+        _say(f"theta dims={dims} prec={precision} ltr={ltr}")
+        X = nze.kernel_theta(_torch_dev(A.reshape(4 * cl, cm), precision),
+                             _torch_dev(B.reshape(cm, 4 * cr), precision), R, ltr)
+        got = X.double().cpu().numpy()
+        if not ltr:
+            got = got.T
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        _say(f"  max rel err {err:.2e}")
+        assert err < tol
+
+
+@pytest.mark.parametrize("precision", [nze.NZE_FP64, nze.NZE_MIXED])
+@pytest.mark.parametrize("shape", [(1024, 1024), (2048, 2048), (1000, 996), (37, 64)])
+def test_kernel_rowortho_known_spectrum(precision, shape):
+    # the block one-sided Jacobi of the layer kernel on X = U diag(s) V^T with
+    # a known spectrum: graded over eight decades with clusters of equal
+    # values, sizes of the chi = 256 and chi = 512 updates and ragged ones
+    R, C = shape
+    k = min(R, C)
+    rng = np.random.default_rng(R + C)
+    Uq, _ = np.linalg.qr(rng.standard_normal((R, k)))
+    Vq, _ = np.linalg.qr(rng.standard_normal((C, k)))
+    s = np.logspace(0, -8, k)
+    s[10:14] = s[10]                      # an exactly degenerate cluster
+    s[k // 2:k // 2 + 3] = s[k // 2]
+    Xin = (Uq * s) @ Vq.T
+    _say(f"rowortho R={R} C={C} prec={precision}")
+    X = _torch_dev(Xin, precision)
+    fp64 = precision == nze.NZE_FP64
+    W, norms, sweeps = nze.kernel_rowortho(X, 1e-13 if fp64 else 2e-6,
+                                           1e-15 if fp64 else 1e-6, max_sweeps=40)
+    Wn = W.double().cpu().numpy()
+    Xo = X.double().cpu().numpy()
+    sv = np.sort(np.sqrt(np.maximum(norms, 0.0)))[::-1]
+    err = np.max(np.abs(sv[:k] - s))
+    orth = np.max(np.abs(Wn @ Wn.T - np.eye(R)))
+    resid = np.max(np.abs(Wn @ Xin - Xo))
+    _say(f"  sweeps={sweeps} max|sigma-s|={err:.2e} |WW^T-I|={orth:.2e} |W X - X_out|={resid:.2e}")
+    # float32: every visit rotates a row by a 32-term sum (~sqrt(32) 2^-24
+    # relative), and a row takes ~sweeps x rounds visits, so the singular
+    # values carry ~1e-5 relative rounding after the ~1000 visits of a hard
+    # 1024-row input; float64 stays at the 1e-13 level
+    tol = 1e-11 if fp64 else 5e-5
+    assert err < tol and orth < tol and resid < tol
+    assert np.all(sv[k:] < tol)           # rows beyond the rank are zero
+    # rows of the result are mutually orthogonal: the cosine bound is
+    # tol (1 + (tol_abs/tol) ||X|| / ||row||), so check rows well above the
+    # absolute floor
+    nr = np.sqrt(np.einsum("ij,ij->i", Xo, Xo))
+    big = nr > (1e-2 if fp64 else 0.1)
+    G = Xo[big] @ Xo[big].T / np.outer(nr[big], nr[big])
+    assert np.max(np.abs(G - np.diag(np.diag(G)))) < (1e-11 if fp64 else 1e-4)
+
+
+def test_full_size_first_layers_against_oracle():
+    # the n = 50, chi = 256, eight-level workload in the launch configuration
+    # the benchmark times (all levels in one launch per layer), first six
+    # layers: the middle bonds reach chi and are truncated from layer 5 on.
+    # Sampled levels 0 and 7 against the oracle, float64 path, every <Z_i>
+    # and the workload's two observables.
+    w = workloads.noise_sweep_n50(seed=0)
+    layers = w.circuit()[:6]
+    obs = workloads.z_singles(w.n) + list(w.observables)
+    _say("full size n=50 chi=256 L=8 depth 6 fp64")
+    g = _gpu_run(w.n, layers, w.noise, w.factors, w.chi, nze.NZE_FP64)
+    vals, fid, tr = g.expect(obs)
+    st, bonds = g.stats()
+    assert bonds.max() == w.chi
+    for j in (0, 7):
+        nz = ptm.Noise(**w.noise).scaled(w.factors[j])
+        m = ompo.PauliMPO(w.n, w.chi)
+        for ls, us in layers:
+            m.apply_layer(ls, [ptm.ptm_noisy_gate(U, nz) for U in us])
+        err = np.max(np.abs(vals[j] - m.expectations(obs)))
+        _say(f"  level {j}: max|dO|={err:.3e} F_gpu={fid[j]:.12f} F_orc={m.fidelity:.12f} "
+             f"min gap {st[j]['min_cut_gap']:.2e}")
+        assert err < FP64_TOL
+        assert abs(fid[j] - m.fidelity) < FP64_TOL
+
+
 def test_invalid_layer_rejected():
     m = nze.MPO(6, 8, 1, nze.NZE_FP64)
     with pytest.raises(nze.NzeError) as e:
