@@ -84,6 +84,35 @@ typedef struct nze_noise {
 int nze_build_ptm(const double* u_re, const double* u_im,
                   const nze_noise* noise, double scale, double* ptm_out);
 
+/* PTM of a two-qubit gate followed by a general two-qubit Pauli channel
+ * rho -> sum_s p_s s rho s (Sec. 2.2.1 noise families; e.g. the cat-qubit CX
+ * of App. C.2 with error Z on the control 3 lambda, Z on the target
+ * lambda / 2, ZZ lambda / 2).
+ *   rates  : 16 float64, index 4 a + b for the error s_a (x) s_b on (left,
+ *            right); p_s = lambda * rates[s] for s != 0 and the identity
+ *            keeps the rest.  rates[0] is ignored.
+ * Returns NZE_EINVAL on NULL arguments, negative rates or lambda, or
+ * probabilities outside [0, 1]. */
+int nze_build_ptm_pauli(const double* u_re, const double* u_im,
+                        const double* rates, double lambda, double* ptm_out);
+
+/* Folds a noisy single-qubit gate into a two-qubit PTM: the 2x2 unitary u
+ * (row-major real / imaginary parts) followed by the single-qubit Pauli
+ * channel with p_s = lambda * rates[s], s = X, Y, Z at rates[1..3]
+ * (rates[0] ignored; e.g. the cat-qubit Z(theta): Z lambda; H: Z 3 lambda,
+ * X 2 lambda), acting on qubit 0 (left) or 1 (right) of the pair, applied
+ * after (after != 0) or before the gate of ptm_in.  ptm_out may equal ptm_in.
+ * Exact composition: valid when nothing else acts on that qubit in between.
+ * Returns NZE_EINVAL as nze_build_ptm_pauli, or for qubit not 0/1. */
+int nze_ptm_compose_1q(const double* ptm_in, const double* u_re,
+                       const double* u_im, const double* rates, double lambda,
+                       int32_t qubit, int32_t after, double* ptm_out);
+
+/* ptm_out = second * first: the channel `first` followed by `second` on the
+ * same pair, as one subcircuit (Sec. 2.1.2 allows any partition into
+ * subcircuits).  ptm_out may alias either input.  Host-only. */
+int nze_ptm_compose(const double* first, const double* second, double* ptm_out);
+
 /* ------------------------------------------------------------ MPO handle */
 typedef struct mpo_handle mpo_t;
 

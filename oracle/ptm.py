@@ -138,3 +138,70 @@ def ptm_noisy_gate(U, noise):
     for ks in noise_kraus_sequence(noise):
         R = ptm_kraus(ks) @ R
     return R
+
+
+# ------------------------------------------- cat-qubit noise, 1-qubit gates
+
+# Cat-qubit noise model (App. C.2, table of errors per gate at strength lam):
+# probability per unit lam of each Pauli error after the gate.  CX: control
+# first ("1"), target second ("2").
+CAT_RATES = {
+    "Z": {"Z": 1.0},                              # Z(theta): Z with lam
+    "H": {"Z": 3.0, "X": 2.0},                    # H: Z 3 lam, X 2 lam
+    "CX": {"ZI": 3.0, "IZ": 0.5, "ZZ": 0.5},      # CX: Z1 3 lam, Z2 lam/2, Z1Z2 lam/2
+}
+
+_LETTER = {"I": 0, "X": 1, "Y": 2, "Z": 3}
+
+
+def kraus_pauli_channel(probs):
+    """Kraus operators sqrt(p_s) s of the Pauli channel rho -> sum_s p_s s rho s
+    on one qubit (probs keyed by 'X', ...) or two (keyed by 'ZI', ...); the
+    identity keeps 1 - sum p_s."""
+    nq = len(next(iter(probs))) if probs else 1
+    ks = []
+    rest = 1.0
+    for key, p in probs.items():
+        if p == 0.0:
+            continue
+        if nq == 1:
+            m = PAULI1[_LETTER[key]]
+        else:
+            m = np.kron(PAULI1[_LETTER[key[0]]], PAULI1[_LETTER[key[1]]])
+        ks.append(np.sqrt(p) * m)
+        rest -= p
+    eye = np.eye(2 ** nq, dtype=np.complex128)
+    return [np.sqrt(rest) * eye] + ks
+
+
+def cat_probs(gate, lam):
+    """Error probabilities of a gate of the cat-qubit model at strength lam."""
+    return {k: v * lam for k, v in CAT_RATES[gate].items()}
+
+
+def ptm_gate_pauli(U, probs2):
+    """Two-qubit gate U followed by the two-qubit Pauli channel probs2."""
+    return ptm_kraus(kraus_pauli_channel(probs2)) @ ptm_unitary(U)
+
+
+def ptm_1q_on_pair(u, probs1, qubit):
+    """16x16 PTM of the single-qubit gate u followed by the Pauli channel
+    probs1, on qubit 0 (left) or 1 (right) of a pair, identity on the other:
+    built from the two-qubit Kraus operators (sqrt(p_s) s u) (x) I."""
+    u = np.asarray(u, dtype=np.complex128)
+    ks = [K @ u for K in kraus_pauli_channel(probs1)]
+    if qubit == 0:
+        ks2 = [np.kron(K, I2) for K in ks]
+    else:
+        ks2 = [np.kron(I2, K) for K in ks]
+    return ptm_kraus(ks2)
+
+
+def rz(theta):
+    """Z(theta) = exp(-i theta Z / 2)."""
+    return np.diag([np.exp(-0.5j * theta), np.exp(0.5j * theta)])
+
+
+H1 = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2.0)
+CX_LEFT = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]],
+                   dtype=np.complex128)   # control on the left qubit

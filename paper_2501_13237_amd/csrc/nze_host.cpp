@@ -144,6 +144,121 @@ extern "C" int nze_build_ptm(const double* u_re, const double* u_im,
   return NZE_OK;
 }
 
+namespace {
+
+// Single-qubit Paulis a and b anticommute iff both differ from I and from
+// each other.
+inline int anti1(int a, int b) { return (a != 0 && b != 0 && a != b) ? 1 : 0; }
+
+// Eigenvalues of a Pauli channel rho -> sum_s p_s s rho s on the Pauli basis:
+// f_t = sum_s p_s (-1)^[s and t anticommute].  nq = 1 or 2 qubits; the
+// probabilities are p_s = lambda * rates[s] for s != I and the rest on I.
+bool pauli_channel_diag(int nq, const double* rates, double lambda, double* f) {
+  const int n = nq == 1 ? 4 : 16;
+  double p[16], tot = 0.0;
+  for (int s = 1; s < n; ++s) {
+    if (!(rates[s] >= 0.0)) return false;
+    p[s] = lambda * rates[s];
+    tot += p[s];
+  }
+  p[0] = 1.0 - tot;
+  if (!(lambda >= 0.0) || !(p[0] >= 0.0) || !(p[0] <= 1.0)) return false;
+  for (int t = 0; t < n; ++t) {
+    double v = 0.0;
+    for (int s = 0; s < n; ++s) {
+      const int anti = nq == 1 ? anti1(s, t) : anti1(s >> 2, t >> 2) + anti1(s & 3, t & 3);
+      v += (anti & 1) ? -p[s] : p[s];
+    }
+    f[t] = v;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" int nze_build_ptm_pauli(const double* u_re, const double* u_im,
+                                   const double* rates, double lambda,
+                                   double* ptm_out) {
+  if (!u_re || !u_im || !rates || !ptm_out) return fail(NZE_EINVAL, "null argument");
+  double f[16];
+  if (!pauli_channel_diag(2, rates, lambda, f))
+    return fail(NZE_EINVAL, "Pauli error rates give probabilities outside [0, 1]");
+  cplx U[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) U[i][j] = cplx(u_re[4 * i + j], u_im[4 * i + j]);
+  double R[16][16];
+  unitary_ptm(U, R);
+  for (int p = 0; p < 16; ++p)
+    for (int q = 0; q < 16; ++q) ptm_out[16 * p + q] = f[p] * R[p][q];
+  return NZE_OK;
+}
+
+extern "C" int nze_ptm_compose_1q(const double* ptm_in, const double* u_re,
+                                  const double* u_im, const double* rates,
+                                  double lambda, int32_t qubit, int32_t after,
+                                  double* ptm_out) {
+  if (!ptm_in || !u_re || !u_im || !rates || !ptm_out)
+    return fail(NZE_EINVAL, "null argument");
+  if (qubit != 0 && qubit != 1) return fail(NZE_EINVAL, "qubit must be 0 (left) or 1 (right)");
+  double f[4];
+  if (!pauli_channel_diag(1, rates, lambda, f))
+    return fail(NZE_EINVAL, "Pauli error rates give probabilities outside [0, 1]");
+  // r[p][q] = f_p Tr(s_p u s_q u^dagger) / 2
+  cplx u[2][2], ud[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) u[i][j] = cplx(u_re[2 * i + j], u_im[2 * i + j]);
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) ud[i][j] = std::conj(u[j][i]);
+  double r[4][4];
+  for (int q = 0; q < 4; ++q) {
+    cplx sq[2][2], t[2][2], m[2][2];
+    pauli1(q, sq);
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) t[i][j] = u[i][0] * sq[0][j] + u[i][1] * sq[1][j];
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) m[i][j] = t[i][0] * ud[0][j] + t[i][1] * ud[1][j];
+    for (int p = 0; p < 4; ++p) {
+      cplx sp[2][2];
+      pauli1(p, sp);
+      cplx tr = 0;
+      for (int i = 0; i < 2; ++i)
+        for (int k = 0; k < 2; ++k) tr += sp[i][k] * m[k][i];
+      r[p][q] = f[p] * tr.real() / 2.0;
+    }
+  }
+  // embedding on the pair, index 4 p_left + p_right
+  double E[16][16] = {};
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      for (int c = 0; c < 4; ++c)
+        for (int d = 0; d < 4; ++d)
+          E[4 * a + b][4 * c + d] = qubit == 0 ? (b == d ? r[a][c] : 0.0)
+                                              : (a == c ? r[b][d] : 0.0);
+  double Rin[16][16], Rout[16][16];
+  for (int p = 0; p < 16; ++p)
+    for (int q = 0; q < 16; ++q) Rin[p][q] = ptm_in[16 * p + q];
+  if (after) mul16(E, Rin, Rout);
+  else mul16(Rin, E, Rout);
+  for (int p = 0; p < 16; ++p)
+    for (int q = 0; q < 16; ++q) ptm_out[16 * p + q] = Rout[p][q];
+  return NZE_OK;
+}
+
+extern "C" int nze_ptm_compose(const double* first, const double* second,
+                               double* ptm_out) {
+  if (!first || !second || !ptm_out) return fail(NZE_EINVAL, "null argument");
+  double A[16][16], B[16][16], C[16][16];
+  for (int p = 0; p < 16; ++p)
+    for (int q = 0; q < 16; ++q) {
+      A[p][q] = first[16 * p + q];
+      B[p][q] = second[16 * p + q];
+    }
+  mul16(B, A, C);
+  for (int p = 0; p < 16; ++p)
+    for (int q = 0; q < 16; ++q) ptm_out[16 * p + q] = C[p][q];
+  return NZE_OK;
+}
+
 // ------------------------------------------------------------------- fits
 
 namespace {

@@ -84,6 +84,12 @@ def lib():
     L.nze_build_ptm.argtypes = [c_double_p, c_double_p,
                                 ctypes.POINTER(NzeNoise), ctypes.c_double,
                                 c_double_p]
+    L.nze_build_ptm_pauli.argtypes = [c_double_p, c_double_p, c_double_p,
+                                      ctypes.c_double, c_double_p]
+    L.nze_ptm_compose_1q.argtypes = [c_double_p, c_double_p, c_double_p,
+                                     c_double_p, ctypes.c_double, ctypes.c_int32,
+                                     ctypes.c_int32, c_double_p]
+    L.nze_ptm_compose.argtypes = [c_double_p, c_double_p, c_double_p]
     L.mpo_footprint.argtypes = [ctypes.POINTER(MpoConfig)]
     L.mpo_footprint.restype = ctypes.c_size_t
     L.mpo_init.argtypes = [ctypes.POINTER(ctypes.c_void_p),
@@ -173,6 +179,41 @@ def build_ptm(U, noise=None, scale=1.0):
     nz = noise_struct(noise)
     _check(lib().nze_build_ptm(_dp(re), _dp(im), ctypes.byref(nz),
                                float(scale), _dp(out)))
+    return out
+
+
+def build_ptm_pauli(U, rates, lam):
+    """PTM of U followed by the two-qubit Pauli channel p_s = lam rates[s]."""
+    U = np.asarray(U, dtype=np.complex128)
+    re = np.ascontiguousarray(U.real)
+    im = np.ascontiguousarray(U.imag)
+    r = np.ascontiguousarray(rates, dtype=np.float64).reshape(16)
+    out = np.empty((16, 16))
+    _check(lib().nze_build_ptm_pauli(_dp(re), _dp(im), _dp(r), float(lam), _dp(out)))
+    return out
+
+
+def compose_1q(ptm16, u, rates, lam, qubit, after):
+    """Folds the noisy single-qubit gate (u, then the Pauli channel
+    p_s = lam rates[s]) on qubit 0/1 of the pair into ptm16, after or
+    before it."""
+    u = np.asarray(u, dtype=np.complex128)
+    re = np.ascontiguousarray(u.real)
+    im = np.ascontiguousarray(u.imag)
+    r = np.ascontiguousarray(rates, dtype=np.float64).reshape(4)
+    pin = np.ascontiguousarray(ptm16, dtype=np.float64)
+    out = np.empty((16, 16))
+    _check(lib().nze_ptm_compose_1q(_dp(pin), _dp(re), _dp(im), _dp(r), float(lam),
+                                    int(qubit), int(bool(after)), _dp(out)))
+    return out
+
+
+def ptm_compose(first, second):
+    """second @ first: the PTM of `first` followed by `second`."""
+    a = np.ascontiguousarray(first, dtype=np.float64)
+    b = np.ascontiguousarray(second, dtype=np.float64)
+    out = np.empty((16, 16))
+    _check(lib().nze_ptm_compose(_dp(a), _dp(b), _dp(out)))
     return out
 
 

@@ -107,3 +107,55 @@ def test_footprint_and_config_validation():
     f64 = nze.footprint(nze.make_config(50, 256, 8, nze.NZE_FP64))
     f32 = nze.footprint(nze.make_config(50, 256, 8, nze.NZE_MIXED))
     assert f32 < f64 < 2 * 1024 ** 3
+
+
+def _rates2(probs, lam):
+    r = np.zeros(16)
+    L = {"I": 0, "X": 1, "Y": 2, "Z": 3}
+    for k, p in probs.items():
+        r[4 * L[k[0]] + L[k[1]]] = p / lam
+    return r
+
+
+def _rates1(probs, lam):
+    r = np.zeros(4)
+    L = {"I": 0, "X": 1, "Y": 2, "Z": 3}
+    for k, p in probs.items():
+        r[L[k]] = p / lam
+    return r
+
+
+def test_pauli_channel_ptm_matches_oracle():
+    rng = np.random.default_rng(3)
+    lam = 0.02
+    cases = [(ptm.CX_LEFT, ptm.cat_probs("CX", lam)),
+             (workloads.haar_su4(rng), {"XY": 0.003, "ZI": 0.01, "IY": 0.004, "ZZ": 0.002})]
+    for U, probs in cases:
+        got = nze.build_ptm_pauli(U, _rates2(probs, lam), lam)
+        want = ptm.ptm_gate_pauli(U, probs)
+        assert np.max(np.abs(got - want)) < 1e-14
+    with pytest.raises(nze.NzeError):
+        nze.build_ptm_pauli(np.eye(4), np.full(16, 1.0), 0.5)   # p_I < 0
+
+
+@pytest.mark.parametrize("qubit", [0, 1])
+@pytest.mark.parametrize("after", [0, 1])
+def test_compose_one_qubit_gate_matches_oracle(qubit, after):
+    rng = np.random.default_rng(10 + 2 * qubit + after)
+    lam = 0.015
+    base = ptm.ptm_gate_pauli(workloads.haar_su4(rng), ptm.cat_probs("CX", lam))
+    u = ptm.rz(0.81) @ ptm.H1
+    probs = ptm.cat_probs("H", lam)
+    got = nze.compose_1q(base, u, _rates1(probs, lam), lam, qubit, after)
+    E = ptm.ptm_1q_on_pair(u, probs, qubit)
+    want = E @ base if after else base @ E
+    assert np.max(np.abs(got - want)) < 1e-14
+    with pytest.raises(nze.NzeError):
+        nze.compose_1q(base, u, _rates1(probs, lam), lam, 2, after)
+
+
+def test_ptm_compose_is_second_after_first():
+    rng = np.random.default_rng(5)
+    A = ptm.ptm_unitary(workloads.haar_su4(rng))
+    B = ptm.ptm_gate_pauli(ptm.CX_LEFT, ptm.cat_probs("CX", 0.01))
+    assert np.max(np.abs(nze.ptm_compose(A, B) - B @ A)) < 1e-14

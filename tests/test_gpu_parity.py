@@ -318,6 +318,98 @@ def test_full_size_first_layers_against_oracle():
         assert abs(fid[j] - m.fidelity) < FP64_TOL
 
 
+def _cat_tfim_1d(n, steps, lam, th_zz, th_x):
+    """1D transverse-field Ising Trotter circuit under the cat-qubit noise
+    model: per step exp(-i th_zz Z Z / 2) on even then odd pairs as
+    CX . Z(th_zz) on the target . CX, then exp(-i th_x X / 2) on every qubit
+    as H . Z(th_x) . H, each gate followed by its cat-model Pauli errors.
+    Returns the MPO layers (left sites, PTMs with every single-qubit gate
+    folded into a neighbouring two-qubit subcircuit through the library's
+    host calls) and the plain gate list for the dense simulator."""
+    assert n % 2 == 0
+    L1 = {"I": 0, "X": 1, "Y": 2, "Z": 3}
+
+    def r1(gate):
+        r = np.zeros(4)
+        for k, v in ptm.CAT_RATES[gate].items():
+            r[L1[k]] = v
+        return r
+
+    r2 = np.zeros(16)
+    for k, v in ptm.CAT_RATES["CX"].items():
+        r2[4 * L1[k[0]] + L1[k[1]]] = v
+    cx = nze.build_ptm_pauli(ptm.CX_LEFT, r2, lam)
+    zz = nze.ptm_compose(nze.compose_1q(cx, ptm.rz(th_zz), r1("Z"), lam, 1, True), cx)
+    gates, layers = [], []
+    pending = {}                      # qubit -> number of X blocks to fold
+    for step in range(steps):
+        for parity in (0, 1):
+            ls = list(range(parity, n - 1, 2))
+            ptms = []
+            for k in ls:
+                R = zz.copy()
+                for side, q in ((0, k), (1, k + 1)):
+                    for _ in range(pending.pop(q, 0)):     # X block of the step before
+                        for u, g in ((ptm.H1, "H"), (ptm.rz(th_x), "Z"), (ptm.H1, "H"))[::-1]:
+                            R = nze.compose_1q(R, u, r1(g), lam, side, False)
+                ptms.append(R)
+                gates += [("2q", k, ptm.CX_LEFT, "CX"), ("1q", k + 1, ptm.rz(th_zz), "Z"),
+                          ("2q", k, ptm.CX_LEFT, "CX")]
+            layers.append((np.array(ls, dtype=np.int32), ptms))
+        for q in range(n):
+            pending[q] = pending.get(q, 0) + 1
+            gates += [("1q", q, ptm.H1, "H"), ("1q", q, ptm.rz(th_x), "Z"), ("1q", q, ptm.H1, "H")]
+    # the last X blocks fold after the last two-qubit subcircuit on their qubit
+    for li in (len(layers) - 1, len(layers) - 2):
+        ls, ptms = layers[li]
+        for i, k in enumerate(ls):
+            for side, q in ((0, k), (1, k + 1)):
+                if pending.pop(q, 0):
+                    for u, g in ((ptm.H1, "H"), (ptm.rz(th_x), "Z"), (ptm.H1, "H")):
+                        ptms[i] = nze.compose_1q(ptms[i], u, r1(g), lam, side, True)
+    assert not pending
+    return layers, gates
+
+
+def _dense_cat(n, gates, lam):
+    from oracle import dense
+    rho = dense.product_state([0] * n)
+    for kind, k, U, g in gates:
+        if kind == "2q":
+            rho = dense.apply_two_qubit(rho, n, k, U)
+            ks = ptm.kraus_pauli_channel(ptm.cat_probs(g, lam))
+            rho = sum(dense.apply_two_qubit(rho, n, k, K) for K in ks)
+        else:
+            ks = [K @ U for K in ptm.kraus_pauli_channel(ptm.cat_probs(g, lam))]
+            if k < n - 1:
+                rho = sum(dense.apply_two_qubit(rho, n, k, np.kron(K, ptm.I2)) for K in ks)
+            else:
+                rho = sum(dense.apply_two_qubit(rho, n, k - 1, np.kron(ptm.I2, K)) for K in ks)
+    return rho
+
+
+@pytest.mark.parametrize("precision,tol", [(nze.NZE_FP64, FP64_TOL),
+                                           (nze.NZE_MIXED, MIXED_TOL)])
+def test_cat_noise_tfim_with_one_qubit_gates_against_dense(precision, tol):
+    # single-qubit gates and the cat-qubit noise model (App. C.2 table),
+    # folded into the two-qubit subcircuits on the host, against the dense
+    # density matrix of the same gate list (n = 8, exact at chi = 256)
+    from oracle import dense
+    n, steps, lam = 8, 3, 2e-3
+    layers, gates = _cat_tfim_1d(n, steps, lam, 0.4, 0.3)
+    _say(f"cat tfim n={n} steps={steps} prec={precision}")
+    m = nze.MPO(n, 256, 1, precision)
+    for ls, ptms in layers:
+        m.apply_layer(ls, np.array(ptms)[None])
+    obs = workloads.z_singles(n) + workloads.zz_neighbours(n)
+    vals, fid, _ = m.expect(obs)
+    rho = _dense_cat(n, gates, lam)
+    ref = np.array([dense.expectation(rho, n, o).real for o in obs])
+    err = np.max(np.abs(vals[0] - ref))
+    _say(f"  max|dO|={err:.3e} F={fid[0]:.12f}")
+    assert err < tol and abs(fid[0] - 1.0) < tol
+
+
 def test_invalid_layer_rejected():
     m = nze.MPO(6, 8, 1, nze.NZE_FP64)
     with pytest.raises(nze.NzeError) as e:

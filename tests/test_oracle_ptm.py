@@ -133,3 +133,62 @@ def test_ptm_matches_dense_action(seed):
     rho2 = U @ rho @ U.conj().T
     v2 = np.array([np.trace(ptm.PAULI2[P] @ rho2).real for P in range(16)])
     assert np.max(np.abs(ptm.ptm_unitary(U) @ v - v2)) < 1e-14
+
+
+# ------------------------------------------- cat-qubit noise, 1-qubit gates
+
+
+def _anticommute(a, b):
+    return not np.allclose(a @ b, b @ a)
+
+
+def test_cat_pauli_channels_closed_form():
+    # A Pauli channel is diagonal in the Pauli basis with
+    # f_t = sum_s p_s (-1)^[s, t anticommute]; the commutation is checked on
+    # the matrices themselves, not on the index arithmetic.
+    lam = 0.013
+    for gate, nq in (("Z", 1), ("H", 1), ("CX", 2)):
+        probs = ptm.cat_probs(gate, lam)
+        assert abs(sum(probs.values()) - {"Z": 1, "H": 5, "CX": 4}[gate] * lam) < 1e-15
+        ks = ptm.kraus_pauli_channel(probs)
+        basis = ptm.PAULI1 if nq == 1 else ptm.PAULI2
+        ops = {k: (ptm.PAULI1[ptm._LETTER[k]] if nq == 1 else
+                   np.kron(ptm.PAULI1[ptm._LETTER[k[0]]], ptm.PAULI1[ptm._LETTER[k[1]]]))
+               for k in probs}
+        p0 = 1.0 - sum(probs.values())
+        for ti, t in enumerate(basis):
+            f = p0 + sum(p * (-1.0 if _anticommute(ops[k], t) else 1.0)
+                         for k, p in probs.items())
+            out = sum(K @ t @ K.conj().T for K in ks)
+            assert np.max(np.abs(out - f * t)) < 1e-14
+
+
+def test_cat_hadamard_ptm_closed_form():
+    # H maps X <-> Z and Y -> -Y; then Z (3 lam) and X (2 lam) errors scale
+    # X by 1 - 6 lam, Y by 1 - 10 lam, Z by 1 - 4 lam (on the left qubit,
+    # identity on the right one)
+    lam = 0.01
+    R = ptm.ptm_1q_on_pair(ptm.H1, ptm.cat_probs("H", lam), 0)
+    r = R[0::4, 0::4]                    # right qubit in I
+    want = np.array([[1, 0, 0, 0], [0, 0, 0, 1 - 6 * lam],
+                     [0, 0, -(1 - 10 * lam), 0], [0, 1 - 4 * lam, 0, 0]])
+    assert np.max(np.abs(r - want)) < 1e-14
+    # identity on the other qubit: R = r (x) I
+    assert np.max(np.abs(R - np.kron(r, np.eye(4)))) < 1e-14
+
+
+@pytest.mark.parametrize("qubit", [0, 1])
+def test_one_qubit_gate_on_pair_matches_dense_action(qubit):
+    rng = np.random.default_rng(7 + qubit)
+    A = rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4))
+    rho = A @ A.conj().T
+    rho /= np.trace(rho)
+    u = ptm.rz(0.37) @ ptm.H1
+    probs = ptm.cat_probs("H", 0.02)
+    ks = [K @ u for K in ptm.kraus_pauli_channel(probs)]
+    ks2 = [np.kron(K, ptm.I2) if qubit == 0 else np.kron(ptm.I2, K) for K in ks]
+    rho2 = sum(K @ rho @ K.conj().T for K in ks2)
+    v = np.array([np.trace(ptm.PAULI2[P] @ rho).real for P in range(16)])
+    v2 = np.array([np.trace(ptm.PAULI2[P] @ rho2).real for P in range(16)])
+    R = ptm.ptm_1q_on_pair(u, probs, qubit)
+    assert np.max(np.abs(R @ v - v2)) < 1e-14
