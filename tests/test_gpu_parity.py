@@ -410,6 +410,33 @@ def test_cat_noise_tfim_with_one_qubit_gates_against_dense(precision, tol):
     assert err < tol and abs(fid[0] - 1.0) < tol
 
 
+def test_long_chain_and_empty_layers():
+    # a long chain (n = 600: 300 gates per layer in one launch, bonds
+    # truncated at chi = 16, F ~ 6e-6, smallest cut gap ~ 1e-5) against the
+    # oracle, with an empty layer in between (no gates: a no-op).  Observed:
+    # 6e-14 (FP64), 8e-7 (mixed).
+    n, chi = 600, 16
+    layers = workloads.brickwork(n, 4, seed=51)
+    noise = {"dep": 4e-3, "ad": 1e-3}
+    obs = [workloads.pauli_string(n, {q: "Z"}) for q in (0, 1, 299, 300, 598, 599)] + \
+          [workloads.pauli_string(n, {q: "Z", q + 1: "Z"}) for q in (0, 300, 598)]
+    for prec, tol in ((nze.NZE_FP64, FP64_TOL), (nze.NZE_MIXED, MIXED_TOL)):
+        _say(f"long chain n={n} chi={chi} prec={prec}")
+        m = nze.MPO(n, chi, 2, prec)
+        for t, (ls, us) in enumerate(layers):
+            m.apply_layer(ls, nze.layer_ptms(us, noise, [1.0, 3.0]))
+            if t == 1:
+                m.apply_layer(np.zeros(0, dtype=np.int32), np.zeros((2, 0, 16, 16)))
+        vals, fid, _ = m.expect(obs)
+        orc = _oracle_run(n, layers, noise, [1.0, 3.0], chi,
+                          tie=(1e-10 if prec == nze.NZE_FP64 else 1e-5))
+        for j, o in enumerate(orc):
+            err = np.max(np.abs(vals[j] - o.expectations(obs)))
+            _say(f"  level {j}: max|dO|={err:.3e} F_gpu={fid[j]:.6e} F_orc={o.fidelity:.6e}")
+            assert err < tol
+            assert abs(fid[j] - o.fidelity) < tol * max(1.0, o.fidelity) * 10
+
+
 def test_invalid_layer_rejected():
     m = nze.MPO(6, 8, 1, nze.NZE_FP64)
     with pytest.raises(nze.NzeError) as e:
