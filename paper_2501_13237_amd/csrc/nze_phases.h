@@ -281,26 +281,17 @@ __device__ inline double nr_rsq(double a) {
 // t only sets how much of g_pq the rotation removes: the unrefined hardware
 // reciprocal and root (about 1e-7 relative) leave ~1e-7 g_pq for the next
 // visit.  c must make (c, t c) orthonormal to rounding, so its root is
-// refined.  Two pivots are computed at once, without branches, so that the
-// two dependent chains of reciprocals and roots interleave.
-__device__ inline void jacobi_cs2(double gpp, double gqq, double gpq,
-                                  double hpp, double hqq, double hpq,
-                                  double floor_abs, double& c, double& sn,
-                                  double& c2, double& s2) {
+// refined.
+__device__ inline void jacobi_cs(double gpp, double gqq, double gpq,
+                                 double floor_abs, double& c, double& sn) {
   const bool ra = fabs(gpq) > floor_abs && gpq * gpq > 1e-30 * fabs(gpp * gqq);
-  const bool rb = fabs(hpq) > floor_abs && hpq * hpq > 1e-30 * fabs(hpp * hqq);
   const double ta = (gqq - gpp) * __builtin_amdgcn_rcp(2.0 * (ra ? gpq : 1.0));
-  const double tb = (hqq - hpp) * __builtin_amdgcn_rcp(2.0 * (rb ? hpq : 1.0));
-  const double ua = fma(ta, ta, 1.0), ub = fma(tb, tb, 1.0);
+  const double ua = fma(ta, ta, 1.0);
   const double xa = (ta >= 0 ? 1.0 : -1.0) *
                     __builtin_amdgcn_rcp(fabs(ta) + ua * __builtin_amdgcn_rsq(ua));
-  const double xb = (tb >= 0 ? 1.0 : -1.0) *
-                    __builtin_amdgcn_rcp(fabs(tb) + ub * __builtin_amdgcn_rsq(ub));
-  const double ca = nr_rsq(fma(xa, xa, 1.0)), cb = nr_rsq(fma(xb, xb, 1.0));
+  const double ca = nr_rsq(fma(xa, xa, 1.0));
   c = ra ? ca : 1.0;
   sn = ra ? xa * ca : 0.0;
-  c2 = rb ? cb : 1.0;
-  s2 = rb ? xb * cb : 0.0;
 }
 
 // Round-robin pairing of 32 indices: pair k (0..15) of step st.
@@ -335,17 +326,25 @@ __device__ int inner_eigh(const PairLds& L, int max_inner) {
       int p, q, p2, q2;
       rr_pair32(P, st, p, q);
       rr_pair32(P2, st, p2, q2);
-      // every LDS read of the step is issued before any write (the thread's
-      // four Q entries are its own within the step)
+      // the sixteen rotations of the step are computed once, by lanes 0-15
+      // (one dependent chain each), and read by every thread from LDS
+      if (tid < 16) {
+        int a, b;
+        rr_pair32(tid, st, a, b);
+        double ct, stt;
+        jacobi_cs(Ga[a * GLD + a], Ga[b * GLD + b], Ga[a * GLD + b], floor_abs, ct, stt);
+        L.cs[tid] = ct;
+        L.sn[tid] = stt;
+      }
+      // the thread's G and Q reads are issued before the barrier (the four Q
+      // entries are its own within the step)
       const int u0 = 2 * P;
-      const double gpp = Ga[p * GLD + p], gqq = Ga[q * GLD + q], gpq = Ga[p * GLD + q];
-      const double hpp = Ga[p2 * GLD + p2], hqq = Ga[q2 * GLD + q2], hpq = Ga[p2 * GLD + q2];
       const double g11 = Ga[p * GLD + p2], g12 = Ga[p * GLD + q2];
       const double g21 = Ga[q * GLD + p2], g22 = Ga[q * GLD + q2];
       const double qa = L.Qs[u0 * GLD + p2], qb = L.Qs[u0 * GLD + q2];
       const double qc = L.Qs[(u0 + 1) * GLD + p2], qd = L.Qs[(u0 + 1) * GLD + q2];
-      double c, sn, c2, s2;
-      jacobi_cs2(gpp, gqq, gpq, hpp, hqq, hpq, floor_abs, c, sn, c2, s2);
+      __syncthreads();
+      const double c = L.cs[P], sn = L.sn[P], c2 = L.cs[P2], s2 = L.sn[P2];
       any |= (sn != 0.0);
       const double h11 = c * g11 - sn * g21, h12 = c * g12 - sn * g22;
       const double h21 = sn * g11 + c * g21, h22 = sn * g12 + c * g22;
