@@ -445,8 +445,10 @@ __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
     if (v <= u) continue;
     const double guu = L.Gs[u * GLD + u], gvv = L.Gs[v * GLD + v];
     const double guv = fabs(L.Gs[u * GLD + v]);
-    const double den = sqrt(guu * gvv) + ratio_abs * sqrt(F2 * fmax(guu, gvv));
-    const double q = den > 0.0 ? guv / den : (guv > 0.0 ? 1.0 : 0.0);
+    // a tolerance test: hardware root and reciprocal (~1e-7 relative) suffice
+    const double den = __builtin_amdgcn_sqrt(guu * gvv) +
+                       ratio_abs * __builtin_amdgcn_sqrt(F2 * fmax(guu, gvv));
+    const double q = den > 0.0 ? guv * __builtin_amdgcn_rcp(den) : (guv > 0.0 ? 1.0 : 0.0);
     worst = fmaxf(worst, (q == q) ? float(q) : 1.0f);
   }
   for (int o = 32; o > 0; o >>= 1) worst = fmaxf(worst, __shfl_xor(worst, o, 64));
