@@ -104,13 +104,13 @@ __device__ __forceinline__ void layer_body(const Slot* slots,
   }
 }
 
-// Entry points.  The float kernel is built for two workgroups per CU (at most
-// 256 registers a lane), which doubles the MPOs one launch can hold when
-// serving; the double kernel needs more registers and runs one per CU.
+// Entry points, one workgroup per CU each (the float kernel limited to two
+// workgroups per CU spilled registers once the rotations were vectorised,
+// and one workgroup per CU is what a Jacobi chain uses).
 #define NZE_LAYER_ARGS const Slot* slots, const Step* steps, const double* ptms, \
     int nsteps, int nmpo, int G, int* bar, int* abort_flag,                    \
     unsigned long long timeout, int xcd, const int* wgmap, const int* gsize
-__global__ __launch_bounds__(NT, 2) void k_layer_f32(NZE_LAYER_ARGS) {
+__global__ __launch_bounds__(NT) void k_layer_f32(NZE_LAYER_ARGS) {
   __shared__ double smem[SMEM_DOUBLES];
   __shared__ int sflag[4];
   layer_body<float>(slots, steps, ptms, nsteps, nmpo, G, bar, abort_flag, timeout,

@@ -384,6 +384,42 @@ __device__ void pair_rotate(T* M, int ld, int ncols, const PairLds& L) {
   for (int s = 0; s < 8; ++s) src[s] = L.rows[4 * s + kq];
   int dst0[4], dst1[4];
   for (int r = 0; r < 4; ++r) { dst0[r] = L.rows[mrow<T>(kq, r)]; dst1[r] = L.rows[16 + mrow<T>(kq, r)]; }
+  if ((ld & 3) == 0 && (ncols & 3) == 0 && (reinterpret_cast<uintptr_t>(M) & 15) == 0) {
+    // vector path: lane (i, kq) loads four consecutive columns c0 + 4i .. +3
+    // of row 4s + kq; MFMA j takes column c0 + 4i + j, and each output row's
+    // four columns leave as one vector store
+    for (int c0 = 64 * w; c0 < ncols; c0 += 256) {
+      const int c = c0 + 4 * i;
+      const bool cok = c < ncols;
+      T x[8][4];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[s][j] = T(0);
+        if (cok && src[s] >= 0) load4(M + (size_t)src[s] * ld + c, x[s]);
+      }
+      // two column pairs at a time (fewer live accumulators)
+#pragma unroll
+      for (int jh = 0; jh < 4; jh += 2) {
+        acc_t d0a = {0, 0, 0, 0}, d0b = {0, 0, 0, 0}, d1a = {0, 0, 0, 0}, d1b = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          d0a = mfma4(qa[0][s], x[s][jh], d0a);
+          d0b = mfma4(qa[0][s], x[s][jh + 1], d0b);
+          d1a = mfma4(qa[1][s], x[s][jh], d1a);
+          d1b = mfma4(qa[1][s], x[s][jh + 1], d1b);
+        }
+        if (cok) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (dst0[r] >= 0) store2(M + (size_t)dst0[r] * ld + c + jh, d0a[r], d0b[r]);
+            if (dst1[r] >= 0) store2(M + (size_t)dst1[r] * ld + c + jh, d1a[r], d1b[r]);
+          }
+        }
+      }
+    }
+    return;
+  }
   constexpr int NCH = 4;   // 16-column chunks in flight per wave
   for (int c0 = 16 * w; c0 < ncols; c0 += 64 * NCH) {
     T xb[NCH][8];
