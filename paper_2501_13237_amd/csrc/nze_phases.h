@@ -319,6 +319,7 @@ __device__ int inner_eigh(const PairLds& L, int max_inner) {
   const int P = tid >> 4, P2 = tid & 15;
   double* Ga = L.Gs;
   double* Gb = L.Gp;          // 32 x GLD, free once the Gram is reduced
+  double* csw = L.Gp + 2048 + 32 * (tid >> 6);   // this wave's (c, s) slots
   __syncthreads();
   for (int sw = 0; sw < max_inner; ++sw) {
     int any = 0;
@@ -326,25 +327,30 @@ __device__ int inner_eigh(const PairLds& L, int max_inner) {
       int p, q, p2, q2;
       rr_pair32(P, st, p, q);
       rr_pair32(P2, st, p2, q2);
-      // the sixteen rotations of the step are computed once, by lanes 0-15
-      // (one dependent chain each), and read by every thread from LDS
-      if (tid < 16) {
+      // the sixteen rotations of the step are computed by lanes 0-15 of each
+      // wave (one dependent chain each) and shared inside the wave through its
+      // own LDS slots: a wave's LDS operations complete in order, so no
+      // workgroup barrier is needed
+      if ((tid & 63) < 16) {
+        const int k = tid & 15;
         int a, b;
-        rr_pair32(tid, st, a, b);
+        rr_pair32(k, st, a, b);
         double ct, stt;
         jacobi_cs(Ga[a * GLD + a], Ga[b * GLD + b], Ga[a * GLD + b], floor_abs, ct, stt);
-        L.cs[tid] = ct;
-        L.sn[tid] = stt;
+        csw[k] = ct;
+        csw[16 + k] = stt;
       }
-      // the thread's G and Q reads are issued before the barrier (the four Q
-      // entries are its own within the step)
+      // the thread's G and Q reads (the four Q entries are its own within the
+      // step)
       const int u0 = 2 * P;
       const double g11 = Ga[p * GLD + p2], g12 = Ga[p * GLD + q2];
       const double g21 = Ga[q * GLD + p2], g22 = Ga[q * GLD + q2];
       const double qa = L.Qs[u0 * GLD + p2], qb = L.Qs[u0 * GLD + q2];
       const double qc = L.Qs[(u0 + 1) * GLD + p2], qd = L.Qs[(u0 + 1) * GLD + q2];
-      __syncthreads();
-      const double c = L.cs[P], sn = L.sn[P], c2 = L.cs[P2], s2 = L.sn[P2];
+      __builtin_amdgcn_s_waitcnt(0xc07f);          // lgkmcnt(0)
+      __builtin_amdgcn_wave_barrier();
+      asm volatile("" ::: "memory");
+      const double c = csw[P], sn = csw[16 + P], c2 = csw[P2], s2 = csw[16 + P2];
       any |= (sn != 0.0);
       const double h11 = c * g11 - sn * g21, h12 = c * g12 - sn * g22;
       const double h21 = sn * g11 + c * g21, h22 = sn * g12 + c * g22;
