@@ -231,8 +231,10 @@ int mpo_stats(mpo_t* h, nze_stats* stats, int32_t* bonds);
  * layer kernel, in milliseconds, [n_levels][16]: contraction, block Gram,
  * convergence test, LDS eigen-solve, rotation of the data, rotation of the
  * accumulator, barrier wait inside Jacobi, row norms, selection, absorption,
- * centre-move preparation, centre-move absorption, then (not times) inner
- * Jacobi sweeps and pair solves counted, then 0, then whole-Jacobi time.
+ * centre-move preparation, centre-move absorption, per-sweep overhead of the
+ * Jacobi (row norms, re-sort, and the barriers that open and close a sweep),
+ * then (not a time) the pair solves counted, then the mean barrier wait over
+ * all workgroups, then whole-Jacobi time.
  * Synchronises the stream. */
 int mpo_profile(mpo_t* h, double* ms_out);
 

@@ -52,7 +52,7 @@ struct Slot {
 
 // phase timers of workgroup 0 of each MPO
 enum { PF_THETA = 0, PF_GRAM, PF_CHECK, PF_EIGH, PF_ROTX, PF_ROTW, PF_WAIT,
-       PF_NORMS, PF_SELECT, PF_ABSORB, PF_MOVE_PREP, PF_MOVE_GEMM, PF_EIGH_SW,
+       PF_NORMS, PF_SELECT, PF_ABSORB, PF_MOVE_PREP, PF_MOVE_GEMM, PF_SWEEP,
        PF_PAIRS, PF_WAIT_ALL, PF_N = 16 };
 
 struct PhaseClock {

@@ -857,7 +857,7 @@ extern "C" int mpo_profile(mpo_t* h, double* ms_out) {
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
   for (size_t i = 0; i < t.size(); ++i) {
     const int slot = (int)(i % PF_N);
-    ms_out[i] = (slot == PF_EIGH_SW || slot == PF_PAIRS) ? t[i] : t[i] / khz;
+    ms_out[i] = (slot == PF_PAIRS) ? t[i] : t[i] / khz;
   }
   return NZE_OK;
 }

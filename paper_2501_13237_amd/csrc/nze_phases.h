@@ -307,7 +307,7 @@ __device__ inline void rr_pair32(int k, int st, int& p, int& q) {
 // (the dead Gram partials), so a step needs one barrier.  Thread t owns the
 // 2x2 block (pair t/16, pair t%16) of G and rows 2(t/16), 2(t/16)+1 of Qs
 // at pair t%16.  Returns the sweeps done; the final G is not kept.
-__device__ int inner_eigh(const PairLds& L, int max_inner) {
+__device__ int inner_eigh(const PairLds& L, int max_inner, const double** Gfinal) {
   const int tid = threadIdx.x;
   for (int e = tid; e < 32 * 32; e += NT) {
     const int u = e >> 5, v = e & 31;
@@ -372,8 +372,9 @@ __device__ int inner_eigh(const PairLds& L, int max_inner) {
     __syncthreads();
     const int f = L.flag[0];
     __syncthreads();
-    if (!f) return sw + 1;
+    if (!f) { *Gfinal = Ga; return sw + 1; }
   }
+  *Gfinal = Ga;
   return max_inner;
 }
 
@@ -462,7 +463,7 @@ template <typename T>
 __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
                             int J, int nb, int sw, double F2, double* smem,
                             bool timed, const int* order, Group& grp,
-                            int* verX, int* verW, int target) {
+                            int* verX, int* verW, int target, bool last_round) {
   const PairLds L = pair_lds(smem);
   const int tid = threadIdx.x;
   PhaseClock clk(timed && s.prof != nullptr);
@@ -502,14 +503,20 @@ __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
   const int go = L.flag[1];
   __syncthreads();
   clk.lap(s.prof, PF_CHECK);
+  const double* Gfin = L.Gs;
   if (go) {
     if (tid == 0) atomicAdd(&s.ctr[CT_ROT + sw], 1);
-    const int nsw = inner_eigh(L, INNER_SWEEPS);
+    const int nsw = inner_eigh(L, INNER_SWEEPS, &Gfin);
     clk.lap(s.prof, PF_EIGH);
-    if (clk.on && tid == 0) { s.prof[PF_EIGH_SW] += nsw; s.prof[PF_PAIRS] += 1.0; }
+    if (clk.on && tid == 0) s.prof[PF_PAIRS] += 1.0;
+    (void)nsw;
     pair_rotate<T>(X, C, C, L);
     clk.lap(s.prof, PF_ROTX);
   }
+  // the last round visits every block once: the diagonal of the pair's Gram
+  // after the visit (Q^T G Q when it rotated) gives the squared row norms
+  // that order the next sweep, without a pass over X
+  if (last_round && tid < 32 && L.rows[tid] >= 0) s.norms[L.rows[tid]] = Gfin[tid * GLD + tid];
   blocks_release(grp, verX, I, J);
   // accumulator rows: previous visits of both blocks first, in visit order
   if (!blocks_wait(grp, verW, I, J, target)) return false;
@@ -579,9 +586,14 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
   int sweeps = 0;
   bool conv = false;
   for (int sw = 0; sw < s.max_sweeps && sw < MAXSW; ++sw) {
-    // blocks are consecutive runs of the rows sorted by decreasing norm
-    phase_norms<T>(s, X, R, C, g, G);
-    if (!group_sync(grp)) return false;
+    PhaseClock sclk(g == 0 && s.prof != nullptr);
+    // blocks are consecutive runs of the rows sorted by decreasing norm; the
+    // norms come from a pass over X before the first sweep and from the last
+    // round's visits afterwards
+    if (sw == 0) {
+      phase_norms<T>(s, X, R, C, g, G);
+      if (!group_sync(grp)) return false;
+    }
     if (g == 0) {
       double* key = smem;
       int* idx = reinterpret_cast<int*>(smem + 4 * CHI_LIMIT);
@@ -599,6 +611,7 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
         for (int b = threadIdx.x; b < nbe; b += NT) { ver[b] = 0; wver[b] = 0; }
     }
     if (!group_sync(grp)) return false;
+    sclk.lap(s.prof, PF_SWEEP);
     const double F2 = __hip_atomic_load(&s.scal[SC_F2], __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
     // visit v = t npair + q (pair q of round t) belongs to workgroup v mod G;
@@ -621,12 +634,14 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
           }
         }
         if (!jacobi_pair<T>(s, X, W, R, C, I, J, nb, sw, F2, smem, g == 0, s.perm,
-                            grp, ver, wver, base + t))
+                            grp, ver, wver, base + t, t == rounds - 1))
           return false;
       }
     }
     // every visit of the sweep is complete before the norms are taken
+    sclk.t = sclk.on ? wall_clock64() : 0;
     if (!group_sync(grp)) return false;
+    sclk.lap(s.prof, PF_SWEEP);
     sweeps = sw + 1;
     const int rot = __hip_atomic_load(&s.ctr[CT_ROT + sw], __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);

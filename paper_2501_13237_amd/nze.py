@@ -395,7 +395,7 @@ class MPO:
 
     PROFILE_NAMES = ["theta", "gram", "check", "eigh", "rot_x", "rot_w",
                      "jacobi_wait", "norms", "select", "absorb", "move_prep",
-                     "move_absorb", "inner_sweeps", "pair_solves", "wait_mean",
+                     "move_absorb", "sweep_overhead", "pair_solves", "wait_mean",
                      "jacobi_total"]
 
     def profile(self):
