@@ -33,7 +33,7 @@ __device__ inline int ld_agent(const int* p) {
 //             workgroups evenly over its MPOs, and group barriers stay inside
 //             the XCD's L2.
 // bar: [nmpo] group counters, then 8 per-XCD tickets and the census counter.
-template <typename T>
+template <typename T, int VEC>
 __device__ __forceinline__ void layer_body(const Slot* slots,
                                              const Step* steps,
                                              const double* ptms, int nsteps,
@@ -88,11 +88,11 @@ __device__ __forceinline__ void layer_body(const Slot* slots,
     switch (op.op) {
       case OP_GATE_LR:
       case OP_GATE_RL:
-        ok = op_gate<T>(s, op.k, op.op == OP_GATE_LR, ptms + (size_t)op.ptm * 256, g, G, grp, smem);
+        ok = op_gate<T, VEC>(s, op.k, op.op == OP_GATE_LR, ptms + (size_t)op.ptm * 256, g, G, grp, smem);
         break;
       case OP_MOVE_LR:
       case OP_MOVE_RL:
-        ok = op_move<T>(s, op.k, op.op == OP_MOVE_LR, g, G, grp, smem);
+        ok = op_move<T, VEC>(s, op.k, op.op == OP_MOVE_LR, g, G, grp, smem);
         break;
       default:
         break;
@@ -104,23 +104,31 @@ __device__ __forceinline__ void layer_body(const Slot* slots,
   }
 }
 
-// Entry points, one workgroup per CU each (the float kernel limited to two
-// workgroups per CU spilled registers once the rotations were vectorised,
-// and one workgroup per CU is what a Jacobi chain uses).
+// Entry points.  One workgroup per CU with vectorised rotations is what a
+// Jacobi chain needs (the headline case: one job's levels).
 #define NZE_LAYER_ARGS const Slot* slots, const Step* steps, const double* ptms, \
     int nsteps, int nmpo, int G, int* bar, int* abort_flag,                    \
     unsigned long long timeout, int xcd, const int* wgmap, const int* gsize
 __global__ __launch_bounds__(NT) void k_layer_f32(NZE_LAYER_ARGS) {
   __shared__ double smem[SMEM_DOUBLES];
   __shared__ int sflag[4];
-  layer_body<float>(slots, steps, ptms, nsteps, nmpo, G, bar, abort_flag, timeout,
-                    xcd, wgmap, gsize, smem, sflag);
+  layer_body<float, 1>(slots, steps, ptms, nsteps, nmpo, G, bar, abort_flag, timeout,
+                       xcd, wgmap, gsize, smem, sflag);
+}
+// Two workgroups per CU (at most 256 registers a lane, scalar rotations):
+// for batches whose groups outnumber the CUs, where independent MPOs on one
+// CU hide each other's latencies.
+__global__ __launch_bounds__(NT, 2) void k_layer_f32x2(NZE_LAYER_ARGS) {
+  __shared__ double smem[SMEM_DOUBLES];
+  __shared__ int sflag[4];
+  layer_body<float, 0>(slots, steps, ptms, nsteps, nmpo, G, bar, abort_flag, timeout,
+                       xcd, wgmap, gsize, smem, sflag);
 }
 __global__ __launch_bounds__(NT) void k_layer_f64(NZE_LAYER_ARGS) {
   __shared__ double smem[SMEM_DOUBLES];
   __shared__ int sflag[4];
-  layer_body<double>(slots, steps, ptms, nsteps, nmpo, G, bar, abort_flag, timeout,
-                     xcd, wgmap, gsize, smem, sflag);
+  layer_body<double, 1>(slots, steps, ptms, nsteps, nmpo, G, bar, abort_flag, timeout,
+                        xcd, wgmap, gsize, smem, sflag);
 }
 #undef NZE_LAYER_ARGS
 
@@ -349,6 +357,7 @@ std::map<hipStream_t, Staging*> g_stage;
 struct DevInfo {
   int cus = 0;
   int occ[2] = {0, 0};
+  int occ_f32x2 = 0;        // float kernel built for two workgroups per CU
   unsigned long long timeout_ticks = 0;
   bool xcd_local = false;   // 8 XCDs with their own L2 (gfx950)
 };
@@ -390,6 +399,8 @@ int dev_info(DevInfo& out) {
   di.occ[0] = occ;
   HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_layer_f32, NT, 0));
   di.occ[1] = occ;
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_layer_f32x2, NT, 0));
+  di.occ_f32x2 = occ;
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
     khz = 100000;
@@ -641,12 +652,6 @@ int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& 
   DevInfo di;
   int rc = dev_info(di);
   if (rc) { restore(); return rc; }
-  const int occ = di.occ[prec == NZE_FP64 ? 0 : 1];
-  const int resident = std::max(1, occ * di.cus);
-  if ((int)nmpo > resident) {
-    restore();
-    return fail(NZE_EINVAL, "batch has more MPOs than resident workgroups");
-  }
   // Group size of each MPO: the pairs per Jacobi round at its chi cap
   // (m / 32; a pair visit waits for the previous round's visits of its
   // blocks, so more workgroups than pairs do not shorten the chain of rounds,
@@ -661,6 +666,15 @@ int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& 
   }
   long long want_tot = 0;
   for (int x : gm) want_tot += x;
+  // float batches that ask for more groups than one per CU run the kernel
+  // built for two workgroups per CU (independent MPOs then share each CU)
+  const bool x2 = prec != NZE_FP64 && di.occ_f32x2 >= 2 && want_tot > (long long)di.occ[1] * di.cus;
+  const int occ = prec == NZE_FP64 ? di.occ[0] : (x2 ? di.occ_f32x2 : di.occ[1]);
+  const int resident = std::max(1, occ * di.cus);
+  if ((int)nmpo > resident) {
+    restore();
+    return fail(NZE_EINVAL, "batch has more MPOs than resident workgroups");
+  }
   if (want_tot > resident) {
     const double scale = double(resident) / double(want_tot);
     want_tot = 0;
@@ -734,7 +748,8 @@ int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& 
   void* args[] = {&a_slots, &a_steps, &a_ptm, &a_nsteps, &a_nmpo, &a_G, &a_bar, &a_abort,
                   &a_to, &a_xcd, &a_map, &a_gsz};
   const void* fn = prec == NZE_FP64 ? reinterpret_cast<const void*>(&k_layer_f64)
-                                    : reinterpret_cast<const void*>(&k_layer_f32);
+                   : x2 ? reinterpret_cast<const void*>(&k_layer_f32x2)
+                        : reinterpret_cast<const void*>(&k_layer_f32);
   HIPCHK(hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(NT), args, 0, stream));
   return NZE_OK;
 }

@@ -379,7 +379,7 @@ __device__ int inner_eigh(const PairLds& L, int max_inner, const double** Gfinal
 }
 
 // rows <- Q^T rows for the pair's 32 rows of M (ld, ncols), in place.
-template <typename T>
+template <typename T, int VEC = 1>
 __device__ void pair_rotate(T* M, int ld, int ncols, const PairLds& L) {
   typedef typename AccT<T>::type acc_t;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -391,7 +391,7 @@ __device__ void pair_rotate(T* M, int ld, int ncols, const PairLds& L) {
   for (int s = 0; s < 8; ++s) src[s] = L.rows[4 * s + kq];
   int dst0[4], dst1[4];
   for (int r = 0; r < 4; ++r) { dst0[r] = L.rows[mrow<T>(kq, r)]; dst1[r] = L.rows[16 + mrow<T>(kq, r)]; }
-  if ((ld & 3) == 0 && (ncols & 3) == 0 && (reinterpret_cast<uintptr_t>(M) & 15) == 0) {
+  if (VEC && (ld & 3) == 0 && (ncols & 3) == 0 && (reinterpret_cast<uintptr_t>(M) & 15) == 0) {
     // vector path: lane (i, kq) loads four consecutive columns c0 + 4i .. +3
     // of row 4s + kq; MFMA j takes column c0 + 4i + j, and each output row's
     // four columns leave as one vector store
@@ -459,7 +459,7 @@ __device__ void pair_rotate(T* M, int ld, int ncols, const PairLds& L) {
 }
 
 // One pair step of sweep `sw`: Gram, convergence test, inner solve, rotate.
-template <typename T>
+template <typename T, int VEC = 1>
 __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
                             int J, int nb, int sw, double F2, double* smem,
                             bool timed, const int* order, Group& grp,
@@ -510,7 +510,7 @@ __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
     clk.lap(s.prof, PF_EIGH);
     if (clk.on && tid == 0) s.prof[PF_PAIRS] += 1.0;
     (void)nsw;
-    pair_rotate<T>(X, C, C, L);
+    pair_rotate<T, VEC>(X, C, C, L);
     clk.lap(s.prof, PF_ROTX);
   }
   // the last round visits every block once: the diagonal of the pair's Gram
@@ -520,7 +520,7 @@ __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
   blocks_release(grp, verX, I, J);
   // accumulator rows: previous visits of both blocks first, in visit order
   if (!blocks_wait(grp, verW, I, J, target)) return false;
-  if (go) pair_rotate<T>(W, R, R, L);
+  if (go) pair_rotate<T, VEC>(W, R, R, L);
   blocks_release(grp, verW, I, J);
   clk.lap(s.prof, PF_ROTW);
   return true;
@@ -575,7 +575,7 @@ __device__ inline int tourney_block(int pos, int t, int nbe) {
   return pos == 0 ? 0 : 1 + ((pos - 1 + t) % (nbe - 1));
 }
 
-template <typename T>
+template <typename T, int VEC = 1>
 __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, int C, int g,
                              int G, Group& grp, double* smem) {
   const int nb = (R + BW - 1) / BW;
@@ -633,7 +633,7 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
             atomicAdd(&s.prof[PF_WAIT_ALL], double(now - wclk.t) / G);
           }
         }
-        if (!jacobi_pair<T>(s, X, W, R, C, I, J, nb, sw, F2, smem, g == 0, s.perm,
+        if (!jacobi_pair<T, VEC>(s, X, W, R, C, I, J, nb, sw, F2, smem, g == 0, s.perm,
                             grp, ver, wver, base + t, t == rounds - 1))
           return false;
       }
@@ -734,7 +734,7 @@ __device__ void phase_select(const Slot& s, int R, bool gate, double* smem) {
 
 // ----------------------------------------------------------- full ops
 
-template <typename T>
+template <typename T, int VEC = 1>
 __device__ __forceinline__ bool op_gate(const Slot& s, int k, bool ltr, const double* R, int g,
                         int G, Group& grp, double* smem) {
   const int cl = s.dims[k], cr = s.dims[k + 2];
@@ -745,7 +745,7 @@ __device__ __forceinline__ bool op_gate(const Slot& s, int k, bool ltr, const do
   phase_theta<T>(s, k, ltr, R, g, G, smem);
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_THETA);
-  if (!phase_jacobi<T>(s, X, W, Rr, Cc, g, G, grp, smem)) return false;
+  if (!phase_jacobi<T, VEC>(s, X, W, Rr, Cc, g, G, grp, smem)) return false;
   clk.lap(s.prof, 15);
   phase_norms<T>(s, X, Rr, Cc, g, G);
   if (!group_sync(grp)) return false;
@@ -772,7 +772,7 @@ __device__ __forceinline__ bool op_gate(const Slot& s, int k, bool ltr, const do
 }
 
 // Centre move away from site c: to c+1 (ltr) or c-1.
-template <typename T>
+template <typename T, int VEC = 1>
 __device__ __forceinline__ bool op_move(const Slot& s, int c, bool ltr, int g, int G,
                         Group& grp, double* smem) {
   const int cl = s.dims[c], cr = s.dims[c + 1];
@@ -817,7 +817,7 @@ __device__ __forceinline__ bool op_move(const Slot& s, int c, bool ltr, int g, i
   }
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_MOVE_PREP);
-  if (!phase_jacobi<T>(s, X, W, Rr, Cc, g, G, grp, smem)) return false;
+  if (!phase_jacobi<T, VEC>(s, X, W, Rr, Cc, g, G, grp, smem)) return false;
   clk.lap(s.prof, 15);
   phase_norms<T>(s, X, Rr, Cc, g, G);
   if (!group_sync(grp)) return false;

@@ -437,6 +437,25 @@ def test_long_chain_and_empty_layers():
             assert abs(fid[j] - o.fidelity) < tol * max(1.0, o.fidelity) * 10
 
 
+def test_many_groups_kernel_matches_bitwise():
+    # ten chi = 256 levels ask for 320 groups, more than one per CU: the
+    # launch takes the float kernel built for two workgroups per CU (scalar
+    # rotations).  Each level alone takes the one-per-CU kernel (vector
+    # rotations).  Same arithmetic per element, so identical results.
+    n = 8
+    layers = workloads.brickwork(n, 8, seed=61)
+    obs = workloads.z_singles(n) + workloads.zz_neighbours(n)
+    noise = {"dep": 2e-3}
+    factors = list(np.linspace(1.0, 10.0, 10))
+    _say("many groups: 10 levels chi=256 mixed")
+    m10 = _gpu_run(n, layers, noise, factors, 256, nze.NZE_MIXED)
+    v10, f10, t10 = m10.expect(obs)
+    for j in (0, 9):
+        m1 = _gpu_run(n, layers, noise, [factors[j]], 256, nze.NZE_MIXED)
+        v1, f1, t1 = m1.expect(obs)
+        assert np.array_equal(v10[j], v1[0]) and f10[j] == f1[0] and t10[j] == t1[0]
+
+
 def test_invalid_layer_rejected():
     m = nze.MPO(6, 8, 1, nze.NZE_FP64)
     with pytest.raises(nze.NzeError) as e:
