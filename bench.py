@@ -33,6 +33,7 @@ METRIC = ("MPO two-site updates/s at chi=256 vs plain FP64; extrap. error; "
 
 KERNEL_SOURCES = ["nze_device.h", "nze_phases.h", "nze_mpo.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_layer_traffic_mixed_n50_d24_chi256.md")
+MFMA_FILE = os.path.join(ROOT, "profiles", "k_layer_mfma_counters_mixed_n50_d24_chi256.md")
 
 
 def kernel_sources_sha256():
@@ -44,26 +45,35 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per k_layer launch from the committed counter summary, or
-    None when the kernel sources changed after the counters were taken."""
+def _profile_field(path, key):
+    """A per-launch figure from a committed counter summary, or None when
+    the kernel sources changed after the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             text = f.read()
     except OSError:
         return None
     fields = {}
     for line in text.splitlines():
-        if ":" in line and line.split(":", 1)[0].strip() in (
-                "traffic_bytes_per_launch", "kernel_sources_sha256"):
+        if ":" in line and line.split(":", 1)[0].strip() in (key, "kernel_sources_sha256"):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
     if fields.get("kernel_sources_sha256") != kernel_sources_sha256():
         return None
     try:
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields[key])
     except (KeyError, ValueError):
         return None
+
+
+def measured_traffic():
+    """HBM bytes (calibrated FETCH_SIZE + WRITE_SIZE) per k_layer launch."""
+    return _profile_field(TRAFFIC_FILE, "traffic_bytes_per_launch")
+
+
+def measured_mfma_flops():
+    """Executed FP32 MFMA flops per k_layer launch (SQ_INSTS_VALU_MFMA_MOPS_F32)."""
+    return _profile_field(MFMA_FILE, "mfma_flops_per_launch")
 
 
 def run_job(nze, w, layers, precision, return_mpo=False):
@@ -341,6 +351,8 @@ def main():
                      "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
                      "frac": achieved / PEAK_TFLOPS["f32"],
                      "traffic": measured_traffic(),
+                     "mfma_counter_tflops": (None if measured_mfma_flops() is None else
+                                             measured_mfma_flops() / (np.mean(layer_ms) / 1e3) / 1e12),
                      "kernel": "k_layer (persistent, one launch per layer)",
                      "mean_layer_ms": float(np.mean(layer_ms)),
                      "algorithmic_tflop_per_step": flops_job / 1e12},
