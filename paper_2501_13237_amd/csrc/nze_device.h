@@ -16,7 +16,6 @@ constexpr int GLD = 33;          // LDS leading dimension of 32x32 fp64 tiles
 constexpr int MAXSW = 40;        // sweep-counter slots
 constexpr int CHI_LIMIT = 512;   // largest chi_max (select sorts 4*chi keys)
 constexpr int SMEM_DOUBLES = 6400;
-constexpr int INNER_SWEEPS = 1;  // cyclic sweeps of the LDS solve per pair visit
 
 enum { OP_NONE = 0, OP_GATE_LR = 1, OP_GATE_RL = 2, OP_MOVE_LR = 3,
        OP_MOVE_RL = 4 };

@@ -185,13 +185,10 @@ __device__ void phase_theta(const Slot& s, int k, bool ltr, const double* R,
 
 // LDS layout of one pair step
 struct PairLds {
-  double* Gp;     // [4][1024] per-wave partial Grams
+  double* Gp;     // [4][1024] per-wave partial Grams; during the inner solve
+                  // the second Gram buffer and each wave's (c, s) slots
   double* Gs;     // [32][GLD]
   double* Qs;     // [32][GLD]
-  double* cs;     // [16]
-  double* sn;     // [16]
-  int* pp;        // [16]
-  int* qq;        // [16]
   int* rows;      // [32] global row of each pair row (-1 = none)
   int* flag;      // [2]
 };
@@ -201,13 +198,9 @@ __device__ inline PairLds pair_lds(double* smem) {
   L.Gp = smem;
   L.Gs = L.Gp + 4 * 1024;
   L.Qs = L.Gs + 32 * GLD;
-  L.cs = L.Qs + 32 * GLD;
-  L.sn = L.cs + 16;
-  int* ib = reinterpret_cast<int*>(L.sn + 16);
-  L.pp = ib;
-  L.qq = ib + 16;
-  L.rows = ib + 32;
-  L.flag = ib + 64;
+  int* ib = reinterpret_cast<int*>(L.Qs + 32 * GLD);
+  L.rows = ib;
+  L.flag = ib + 32;
   return L;
 }
 
@@ -300,14 +293,14 @@ __device__ inline void rr_pair32(int k, int st, int& p, int& q) {
   q = 1 + ((30 - k + st) % 31);
 }
 
-// Cyclic parallel Jacobi on the 32x32 symmetric Gs (float64, LDS): up to
-// max_inner sweeps of 31 steps, 16 disjoint rotations per step; Qs
-// accumulates the rotations.  Every thread derives the two rotations it
-// needs from the current G, and G ping-pongs between Gs and a second buffer
-// (the dead Gram partials), so a step needs one barrier.  Thread t owns the
-// 2x2 block (pair t/16, pair t%16) of G and rows 2(t/16), 2(t/16)+1 of Qs
-// at pair t%16.  Returns the sweeps done; the final G is not kept.
-__device__ int inner_eigh(const PairLds& L, int max_inner, const double** Gfinal) {
+// One cyclic parallel Jacobi sweep on the 32x32 symmetric Gs (float64, LDS):
+// 31 steps of 16 disjoint rotations; Qs accumulates the rotations.  Lanes
+// 0-15 of every wave compute the step's rotations into the wave's own LDS
+// slots, and G ping-pongs between Gs and a second buffer (the dead Gram
+// partials), so a step needs one workgroup barrier.  Thread t owns the 2x2
+// block (pair t/16, pair t%16) of G and rows 2(t/16), 2(t/16)+1 of Qs at pair
+// t%16.  Returns the buffer that holds the rotated Gram Q^T G Q.
+__device__ const double* inner_eigh(const PairLds& L) {
   const int tid = threadIdx.x;
   for (int e = tid; e < 32 * 32; e += NT) {
     const int u = e >> 5, v = e & 31;
@@ -321,8 +314,7 @@ __device__ int inner_eigh(const PairLds& L, int max_inner, const double** Gfinal
   double* Gb = L.Gp;          // 32 x GLD, free once the Gram is reduced
   double* csw = L.Gp + 2048 + 32 * (tid >> 6);   // this wave's (c, s) slots
   __syncthreads();
-  for (int sw = 0; sw < max_inner; ++sw) {
-    int any = 0;
+  {
     for (int st = 0; st < 31; ++st) {
       int p, q, p2, q2;
       rr_pair32(P, st, p, q);
@@ -351,7 +343,6 @@ __device__ int inner_eigh(const PairLds& L, int max_inner, const double** Gfinal
       __builtin_amdgcn_wave_barrier();
       asm volatile("" ::: "memory");
       const double c = csw[P], sn = csw[16 + P], c2 = csw[P2], s2 = csw[16 + P2];
-      any |= (sn != 0.0);
       const double h11 = c * g11 - sn * g21, h12 = c * g12 - sn * g22;
       const double h21 = sn * g11 + c * g21, h22 = sn * g12 + c * g22;
       Gb[p * GLD + p2] = c2 * h11 - s2 * h12;
@@ -365,17 +356,8 @@ __device__ int inner_eigh(const PairLds& L, int max_inner, const double** Gfinal
       double* t = Ga; Ga = Gb; Gb = t;
       __syncthreads();
     }
-    if (sw + 1 >= max_inner) break;
-    if (tid == 0) L.flag[0] = 0;
-    __syncthreads();
-    if (any) L.flag[0] = 1;
-    __syncthreads();
-    const int f = L.flag[0];
-    __syncthreads();
-    if (!f) { *Gfinal = Ga; return sw + 1; }
   }
-  *Gfinal = Ga;
-  return max_inner;
+  return Ga;   // the rotated Gram Q^T G Q
 }
 
 // rows <- Q^T rows for the pair's 32 rows of M (ld, ncols), in place.
@@ -506,10 +488,9 @@ __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
   const double* Gfin = L.Gs;
   if (go) {
     if (tid == 0) atomicAdd(&s.ctr[CT_ROT + sw], 1);
-    const int nsw = inner_eigh(L, INNER_SWEEPS, &Gfin);
+    Gfin = inner_eigh(L);
     clk.lap(s.prof, PF_EIGH);
     if (clk.on && tid == 0) s.prof[PF_PAIRS] += 1.0;
-    (void)nsw;
     pair_rotate<T, VEC>(X, C, C, L);
     clk.lap(s.prof, PF_ROTX);
   }
