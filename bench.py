@@ -122,6 +122,53 @@ def saturated_rate(layers, layer_ms, levels, first=6):
             "updates_per_s": 1e3 * upd / ms if ms > 0 else None}
 
 
+def saturated_batches(nze, workloads, batches, first=6, timed=2):
+    """Steady-state two-site updates at saturated chi = 256: B independent
+    n = 50 MPOs (noise levels evenly spaced in [1, 16] x p0, B = 1 at p0) are
+    evolved through the first `first` layers untimed, then `timed` layers are
+    timed, all B MPOs in one launch per layer.  Reports updates/s and the
+    algorithmic FP32 MFMA rate of those launches."""
+    import torch
+    out = {}
+    for B in batches:
+        w = workloads.noise_sweep_n50(seed=0)
+        w.depth = first + timed
+        layers = w.circuit()
+        factors = list(np.linspace(1.0, 16.0, B)) if B > 1 else [1.0]
+        m = nze.MPO(w.n, w.chi, B, nze.NZE_MIXED)
+        try:
+            stream = torch.cuda.current_stream()
+            for ls, us in layers[:first]:
+                m.apply_layer(ls, nze.layer_ptms(us, w.noise, factors))
+            ptms = [nze.layer_ptms(us, w.noise, factors) for _, us in layers[first:]]
+            torch.cuda.synchronize()
+            fl0 = sum(st["flops"] for st in m.stats()[0])
+            ev = []
+            for (ls, _), p in zip(layers[first:], ptms):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                m.apply_layer(ls, p)
+                e1.record(stream)
+                ev.append((e0, e1))
+            torch.cuda.synchronize()
+            ms = sum(a.elapsed_time(b) for a, b in ev)
+            stats, bonds = m.stats()
+            fl = sum(st["flops"] for st in stats) - fl0
+            upd = sum(len(ls) for ls, _ in layers[first:]) * B
+            tf = fl / (ms / 1e3) / 1e12
+            out[str(B)] = {"updates": upd, "kernel_ms": ms,
+                           "updates_per_s": 1e3 * upd / ms,
+                           "achieved_tflops": tf,
+                           "frac": tf / PEAK_TFLOPS["f32"],
+                           "bonds_at_chi": int(np.sum(bonds[0] == w.chi))}
+        finally:
+            m.close()
+        print(f"# saturated batch B={B}: {out[str(B)]['updates_per_s']:.1f} updates/s",
+              file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(w, layers, timed_layer=5, budget_s=40.0):
     """The oracle on noise level 1: evolve the first layers (bonds grow to
     chi), then time one layer whose bonds are saturated."""
@@ -274,6 +321,9 @@ def main():
                     help="skip the n=8 extrapolation-error leg (profiling runs)")
     ap.add_argument("--skip-main", action="store_true",
                     help="only the serving runs")
+    ap.add_argument("--saturated-batches", default="1,8,32,64",
+                    help="batch sizes of the saturated-update microbenchmark "
+                         "(comma list; empty to skip)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many MiB device-to-device five times "
                          "(calibrates the HBM byte counters)")
@@ -374,6 +424,9 @@ def main():
         out["speedup_mixed_vs_fp64"] = value / v64
         out["mixed_vs_fp64_max_abs_obs"] = float(np.max(np.abs(vals - vals64)))
         out["mixed_vs_fp64_max_rel_fid"] = float(np.max(np.abs(fid - fid64) / fid64))
+    if args.saturated_batches:
+        out["saturated_batch"] = saturated_batches(
+            nze, workloads, [int(b) for b in args.saturated_batches.split(",")])
     if not args.no_extrapolation_error:
         out["extrapolation_error_n8"] = extrapolation_error(nze, workloads)
     if not args.no_cpu_baseline:
