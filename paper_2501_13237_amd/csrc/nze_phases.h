@@ -287,19 +287,31 @@ __device__ inline void jacobi_cs(double gpp, double gqq, double gpq,
   sn = ra ? xa * ca : 0.0;
 }
 
-// Round-robin pairing of 32 indices: pair k (0..15) of step st.
-__device__ inline void rr_pair32(int k, int st, int& p, int& q) {
-  p = (k == 0) ? 0 : 1 + ((k - 1 + st) % 31);
-  q = 1 + ((30 - k + st) % 31);
+// Pairing of the 32 rows of a block pair (rows 0-15: block I, 16-31: block
+// J) in one cyclic sweep of 31 steps of 16 disjoint rotations, cross-block
+// pairs first: steps 0-15 pair row k of I with row 16 + (k + st) mod 16 of J
+// (all 256 cross pairs); steps 16-30 are a round-robin tournament inside each
+// block (pairs 0-7 in I, 8-15 in J; all 2 x 120 intra pairs).
+__device__ inline void sweep_pair32(int k, int st, int& p, int& q) {
+  if (st < 16) {
+    p = k;
+    q = 16 + ((k + st) & 15);
+    return;
+  }
+  const int r = st - 16, base = k < 8 ? 0 : 16, j = k & 7;
+  p = base + (j == 0 ? 0 : 1 + ((j - 1 + r) % 15));
+  q = base + 1 + ((14 - j + r) % 15);
 }
 
-// One cyclic parallel Jacobi sweep on the 32x32 symmetric Gs (float64, LDS):
-// 31 steps of 16 disjoint rotations; Qs accumulates the rotations.  Lanes
-// 0-15 of every wave compute the step's rotations into the wave's own LDS
-// slots, and G ping-pongs between Gs and a second buffer (the dead Gram
-// partials), so a step needs one workgroup barrier.  Thread t owns the 2x2
-// block (pair t/16, pair t%16) of G and rows 2(t/16), 2(t/16)+1 of Qs at pair
-// t%16.  Returns the buffer that holds the rotated Gram Q^T G Q.
+// One cyclic parallel Jacobi sweep on the 32x32 symmetric Gs (float64, LDS),
+// cross-block steps first (both blocks enter with nearly orthogonal rows
+// once a sweep has visited them, so the cross entries carry most of the
+// off-diagonal weight); Qs accumulates the rotations.  Lanes 0-15 of every
+// wave compute the step's rotations into the wave's own LDS slots, and G
+// ping-pongs between Gs and a second buffer (the dead Gram partials), so a
+// step needs one workgroup barrier.  Thread t owns the 2x2 block (pair t/16,
+// pair t%16) of G and rows 2(t/16), 2(t/16)+1 of Qs at pair t%16.  Returns
+// the buffer that holds the rotated Gram Q^T G Q.
 __device__ const double* inner_eigh(const PairLds& L) {
   const int tid = threadIdx.x;
   for (int e = tid; e < 32 * 32; e += NT) {
@@ -314,48 +326,46 @@ __device__ const double* inner_eigh(const PairLds& L) {
   double* Gb = L.Gp;          // 32 x GLD, free once the Gram is reduced
   double* csw = L.Gp + 2048 + 32 * (tid >> 6);   // this wave's (c, s) slots
   __syncthreads();
-  {
-    for (int st = 0; st < 31; ++st) {
-      int p, q, p2, q2;
-      rr_pair32(P, st, p, q);
-      rr_pair32(P2, st, p2, q2);
-      // the sixteen rotations of the step are computed by lanes 0-15 of each
-      // wave (one dependent chain each) and shared inside the wave through its
-      // own LDS slots: a wave's LDS operations complete in order, so no
-      // workgroup barrier is needed
-      if ((tid & 63) < 16) {
-        const int k = tid & 15;
-        int a, b;
-        rr_pair32(k, st, a, b);
-        double ct, stt;
-        jacobi_cs(Ga[a * GLD + a], Ga[b * GLD + b], Ga[a * GLD + b], floor_abs, ct, stt);
-        csw[k] = ct;
-        csw[16 + k] = stt;
-      }
-      // the thread's G and Q reads (the four Q entries are its own within the
-      // step)
-      const int u0 = 2 * P;
-      const double g11 = Ga[p * GLD + p2], g12 = Ga[p * GLD + q2];
-      const double g21 = Ga[q * GLD + p2], g22 = Ga[q * GLD + q2];
-      const double qa = L.Qs[u0 * GLD + p2], qb = L.Qs[u0 * GLD + q2];
-      const double qc = L.Qs[(u0 + 1) * GLD + p2], qd = L.Qs[(u0 + 1) * GLD + q2];
-      __builtin_amdgcn_s_waitcnt(0xc07f);          // lgkmcnt(0)
-      __builtin_amdgcn_wave_barrier();
-      asm volatile("" ::: "memory");
-      const double c = csw[P], sn = csw[16 + P], c2 = csw[P2], s2 = csw[16 + P2];
-      const double h11 = c * g11 - sn * g21, h12 = c * g12 - sn * g22;
-      const double h21 = sn * g11 + c * g21, h22 = sn * g12 + c * g22;
-      Gb[p * GLD + p2] = c2 * h11 - s2 * h12;
-      Gb[p * GLD + q2] = s2 * h11 + c2 * h12;
-      Gb[q * GLD + p2] = c2 * h21 - s2 * h22;
-      Gb[q * GLD + q2] = s2 * h21 + c2 * h22;
-      L.Qs[u0 * GLD + p2] = c2 * qa - s2 * qb;
-      L.Qs[u0 * GLD + q2] = s2 * qa + c2 * qb;
-      L.Qs[(u0 + 1) * GLD + p2] = c2 * qc - s2 * qd;
-      L.Qs[(u0 + 1) * GLD + q2] = s2 * qc + c2 * qd;
-      double* t = Ga; Ga = Gb; Gb = t;
-      __syncthreads();
+  for (int st = 0; st < 31; ++st) {
+    int p, q, p2, q2;
+    sweep_pair32(P, st, p, q);
+    sweep_pair32(P2, st, p2, q2);
+    // the sixteen rotations of the step are computed by lanes 0-15 of each
+    // wave (one dependent chain each) and shared inside the wave through its
+    // own LDS slots: a wave's LDS operations complete in order, so no
+    // workgroup barrier is needed
+    if ((tid & 63) < 16) {
+      const int k = tid & 15;
+      int a, b;
+      sweep_pair32(k, st, a, b);
+      double ct, stt;
+      jacobi_cs(Ga[a * GLD + a], Ga[b * GLD + b], Ga[a * GLD + b], floor_abs, ct, stt);
+      csw[k] = ct;
+      csw[16 + k] = stt;
     }
+    // the thread's G and Q reads (the four Q entries are its own within the
+    // step)
+    const int u0 = 2 * P;
+    const double g11 = Ga[p * GLD + p2], g12 = Ga[p * GLD + q2];
+    const double g21 = Ga[q * GLD + p2], g22 = Ga[q * GLD + q2];
+    const double qa = L.Qs[u0 * GLD + p2], qb = L.Qs[u0 * GLD + q2];
+    const double qc = L.Qs[(u0 + 1) * GLD + p2], qd = L.Qs[(u0 + 1) * GLD + q2];
+    __builtin_amdgcn_s_waitcnt(0xc07f);          // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+    const double c = csw[P], sn = csw[16 + P], c2 = csw[P2], s2 = csw[16 + P2];
+    const double h11 = c * g11 - sn * g21, h12 = c * g12 - sn * g22;
+    const double h21 = sn * g11 + c * g21, h22 = sn * g12 + c * g22;
+    Gb[p * GLD + p2] = c2 * h11 - s2 * h12;
+    Gb[p * GLD + q2] = s2 * h11 + c2 * h12;
+    Gb[q * GLD + p2] = c2 * h21 - s2 * h22;
+    Gb[q * GLD + q2] = s2 * h21 + c2 * h22;
+    L.Qs[u0 * GLD + p2] = c2 * qa - s2 * qb;
+    L.Qs[u0 * GLD + q2] = s2 * qa + c2 * qb;
+    L.Qs[(u0 + 1) * GLD + p2] = c2 * qc - s2 * qd;
+    L.Qs[(u0 + 1) * GLD + q2] = s2 * qc + c2 * qd;
+    double* t = Ga; Ga = Gb; Gb = t;
+    __syncthreads();
   }
   return Ga;   // the rotated Gram Q^T G Q
 }
