@@ -13,7 +13,11 @@ lambda_j = (1 + 15 j / 7) p0, chi = 256; observables <Z_25>, <X_1 X_2>.
 588 gates x 8 levels = 4704 two-site updates per job.
 
 Prints one JSON line (rank 0).  `value` is two-site updates/s of the mixed
-(float32 MFMA) path; the plain float64 path is timed beside it.
+(float32 MFMA) path; the plain float64 path is timed beside it.  Also
+reported: p50/p99 job latency of the serving loop on a short Poisson stream
+of mixed jobs, steady-state saturated updates at batch sizes 1-64, the NZNE
+error of the n = 8 workload against dense values, and the oracle on the host
+cores.
 """
 import argparse
 import json
@@ -313,8 +317,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--depth", type=int, default=None,
                     help="override the depth (diagnostics only)")
-    ap.add_argument("--serve", type=int, default=0,
-                    help="also run the serving loop on this many jobs")
+    ap.add_argument("--serve", type=int, default=8,
+                    help="also run the serving loop on this many jobs "
+                         "(0 to skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-sustainable-rate", type=float, default=0.0)
     ap.add_argument("--no-extrapolation-error", action="store_true",
@@ -424,6 +429,9 @@ def main():
         out["speedup_mixed_vs_fp64"] = value / v64
         out["mixed_vs_fp64_max_abs_obs"] = float(np.max(np.abs(vals - vals64)))
         out["mixed_vs_fp64_max_rel_fid"] = float(np.max(np.abs(fid - fid64) / fid64))
+    if args.serve:
+        out["serving"] = serve_run(nze, serve_jobs(args.serve, 1, workloads, nze),
+                                   args.serve_rate, 1, nze.NZE_MIXED)
     if args.saturated_batches:
         out["saturated_batch"] = saturated_batches(
             nze, workloads, [int(b) for b in args.saturated_batches.split(",")])
