@@ -310,9 +310,10 @@ __device__ inline void sweep_pair32(int k, int st, int& p, int& q) {
 // wave compute the step's rotations into the wave's own LDS slots, and G
 // ping-pongs between Gs and a second buffer (the dead Gram partials), so a
 // step needs one workgroup barrier.  Thread t owns the 2x2 block (pair t/16,
-// pair t%16) of G and rows 2(t/16), 2(t/16)+1 of Qs at pair t%16.  Returns
-// the buffer that holds the rotated Gram Q^T G Q.
-__device__ const double* inner_eigh(const PairLds& L) {
+// pair t%16) of G and rows 2(t/16), 2(t/16)+1 of Qs at pair t%16.  With
+// cross_only the sweep stops after the 16 cross-block steps.  Returns the
+// buffer that holds the rotated Gram Q^T G Q.
+__device__ const double* inner_eigh(const PairLds& L, bool cross_only) {
   const int tid = threadIdx.x;
   for (int e = tid; e < 32 * 32; e += NT) {
     const int u = e >> 5, v = e & 31;
@@ -326,7 +327,8 @@ __device__ const double* inner_eigh(const PairLds& L) {
   double* Gb = L.Gp;          // 32 x GLD, free once the Gram is reduced
   double* csw = L.Gp + 2048 + 32 * (tid >> 6);   // this wave's (c, s) slots
   __syncthreads();
-  for (int st = 0; st < 31; ++st) {
+  const int nsteps = cross_only ? 16 : 31;
+  for (int st = 0; st < nsteps; ++st) {
     int p, q, p2, q2;
     sweep_pair32(P, st, p, q);
     sweep_pair32(P2, st, p2, q2);
@@ -455,7 +457,8 @@ template <typename T, int VEC = 1>
 __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
                             int J, int nb, int sw, double F2, double* smem,
                             bool timed, const int* order, Group& grp,
-                            int* verX, int* verW, int target, bool last_round) {
+                            int* verX, int* verW, int target, bool last_round,
+                            bool cross_only) {
   const PairLds L = pair_lds(smem);
   const int tid = threadIdx.x;
   PhaseClock clk(timed && s.prof != nullptr);
@@ -498,7 +501,7 @@ __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
   const double* Gfin = L.Gs;
   if (go) {
     if (tid == 0) atomicAdd(&s.ctr[CT_ROT + sw], 1);
-    Gfin = inner_eigh(L);
+    Gfin = inner_eigh(L, cross_only);
     clk.lap(s.prof, PF_EIGH);
     if (clk.on && tid == 0) s.prof[PF_PAIRS] += 1.0;
     pair_rotate<T, VEC>(X, C, C, L);
@@ -605,6 +608,17 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
     sclk.lap(s.prof, PF_SWEEP);
     const double F2 = __hip_atomic_load(&s.scal[SC_F2], __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
+    // early sweeps of a large problem (64 blocks or more), while every pair
+    // still rotated in the sweep before: the inner solves take only their 256
+    // cross-block rotations.  Far from convergence the outer sweeps, not the
+    // pair solves, set the pace, and the rows are re-blocked by norm at every
+    // sweep, so pairs left inside a block meet as cross pairs later; every
+    // later sweep runs full inner sweeps, which polish all pairs.
+    bool cross_only = false;
+    if (nb >= 64 && sw < 4)
+      cross_only = sw == 0 ||
+                   __hip_atomic_load(&s.ctr[CT_ROT + sw - 1], __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT) == rounds * npair;
     // visit v = t npair + q (pair q of round t) belongs to workgroup v mod G;
     // each workgroup takes its visits in increasing order, and a visit waits
     // only for the previous round's visits of its two blocks, so rounds
@@ -625,7 +639,7 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
           }
         }
         if (!jacobi_pair<T, VEC>(s, X, W, R, C, I, J, nb, sw, F2, smem, g == 0, s.perm,
-                            grp, ver, wver, base + t, t == rounds - 1))
+                            grp, ver, wver, base + t, t == rounds - 1, cross_only))
           return false;
       }
     }
