@@ -615,7 +615,7 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
     // sweep, so pairs left inside a block meet as cross pairs later; every
     // later sweep runs full inner sweeps, which polish all pairs.
     bool cross_only = false;
-    if (nb >= 64 && sw < 4)
+    if (nb >= 64 && sw < 6)
       cross_only = sw == 0 ||
                    __hip_atomic_load(&s.ctr[CT_ROT + sw - 1], __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT) == rounds * npair;
