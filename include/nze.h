@@ -113,6 +113,36 @@ int nze_ptm_compose_1q(const double* ptm_in, const double* u_re,
  * subcircuits).  ptm_out may alias either input.  Host-only. */
 int nze_ptm_compose(const double* first, const double* second, double* ptm_out);
 
+/* The same channel with its two qubits exchanged:
+ * out[4a + b][4c + d] = in[4b + a][4d + c] (the gate acting on (right, left)
+ * of a pair).  ptm_out may equal ptm_in.  Host-only. */
+int nze_ptm_swap_qubits(const double* ptm_in, double* ptm_out);
+
+/* Routing of two-qubit gates on arbitrary qubit pairs onto the open chain by
+ * noiseless nearest-neighbour exchanges (SWAP gates), for circuits on 2D
+ * lattices laid out along the chain (Sec. 3 orders the lattice qubits
+ * column- or row-major).  Logical qubit q starts on chain site q; for each
+ * input gate g, in order, the qubit qb[g] is moved towards qa[g] by SWAPs
+ * until the two are neighbours, then the gate is applied; qubits are not
+ * moved back.
+ *   n        : chain length (>= 2); n_gates: input gates (>= 0).
+ *   qa, qb   : n_gates logical qubit pairs, 0 <= qa, qb < n, qa != qb
+ *              (qa is the first qubit of the gate's 4x4 matrix).
+ *   max_ops  : capacity of the three output arrays.
+ *   op_site  : left chain site s of each op, acting on sites (s, s+1).
+ *   op_gate  : input gate index of the op, or -1 for a SWAP.
+ *   op_flip  : 1 when qa of the gate sits on site s+1 (apply its PTM with
+ *              the qubits exchanged, nze_ptm_swap_qubits), else 0.
+ *   n_ops    : number of ops of the routed sequence (also on NZE_ENOMEM).
+ *   perm_out : NULL or n entries: chain site of each logical qubit after the
+ *              last op (Pauli strings are read out through it).
+ * The three op arrays may be NULL together to query n_ops (NZE_OK).
+ * Host-only.  Errors: NZE_EINVAL (bad sizes or qubits), NZE_ENOMEM (op
+ * arrays given and max_ops < n_ops). */
+int nze_route_chain(int32_t n, int32_t n_gates, const int32_t* qa, const int32_t* qb,
+                    int32_t max_ops, int32_t* op_site, int32_t* op_gate,
+                    uint8_t* op_flip, int32_t* n_ops, int32_t* perm_out);
+
 /* ------------------------------------------------------------ MPO handle */
 typedef struct mpo_handle mpo_t;
 

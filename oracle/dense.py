@@ -50,6 +50,31 @@ def apply_noisy_gate(rho, n, k, U, noise):
     return rho
 
 
+def apply_pair(rho, n, a, b, K):
+    """rho -> K rho K^dagger for a 4x4 operator K on any two distinct qubits
+    (a, b), a being the more significant index of K: the action of a
+    two-qubit gate on the dense density matrix, for circuits whose gates are
+    not nearest neighbours on the chain (2D lattices, Sec. 3)."""
+    K4 = np.asarray(K, dtype=np.complex128).reshape(2, 2, 2, 2)
+    t = rho.reshape((2,) * (2 * n))
+    t = np.tensordot(K4, t, axes=([2, 3], [a, b]))
+    t = np.moveaxis(t, [0, 1], [a, b])
+    t = np.tensordot(K4.conj(), t, axes=([2, 3], [n + a, n + b]))
+    t = np.moveaxis(t, [0, 1], [n + a, n + b])
+    return t.reshape(2 ** n, 2 ** n)
+
+
+def apply_noisy_gate_pair(rho, n, a, b, U, noise):
+    """The noisy gate C o U (Sec. 2.2.1) on qubits (a, b), any a != b."""
+    rho = apply_pair(rho, n, a, b, U)
+    for kraus in noise_kraus_sequence(noise):
+        out = np.zeros_like(rho)
+        for K in kraus:
+            out += apply_pair(rho, n, a, b, K)
+        rho = out
+    return rho
+
+
 def run_circuit(n, layers, noise, init_bits=None):
     """Simulate a list of layers; each layer is a list of (k, U) gates acting
     on qubits (k, k+1).  Gates of one layer act on disjoint pairs, so their

@@ -2,10 +2,12 @@
 // gates (Sec. 2.2.1), the noise-strength extrapolations of Sec. 2.2.2 (B) and
 // App. B.2, the fidelity extrapolation of Sec. 2.2.2 (A) with App. B.1's
 // criterion, and the error strings.
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstring>
 #include <string>
+#include <cstdlib>
 #include <vector>
 
 #include "nze.h"
@@ -256,6 +258,62 @@ extern "C" int nze_ptm_compose(const double* first, const double* second,
   mul16(B, A, C);
   for (int p = 0; p < 16; ++p)
     for (int q = 0; q < 16; ++q) ptm_out[16 * p + q] = C[p][q];
+  return NZE_OK;
+}
+
+extern "C" int nze_ptm_swap_qubits(const double* ptm_in, double* ptm_out) {
+  if (!ptm_in || !ptm_out) return fail(NZE_EINVAL, "null argument");
+  double T[16][16];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      for (int c = 0; c < 4; ++c)
+        for (int d = 0; d < 4; ++d) T[4 * a + b][4 * c + d] = ptm_in[16 * (4 * b + a) + 4 * d + c];
+  for (int p = 0; p < 16; ++p)
+    for (int q = 0; q < 16; ++q) ptm_out[16 * p + q] = T[p][q];
+  return NZE_OK;
+}
+
+extern "C" int nze_route_chain(int32_t n, int32_t n_gates, const int32_t* qa,
+                               const int32_t* qb, int32_t max_ops, int32_t* op_site,
+                               int32_t* op_gate, uint8_t* op_flip, int32_t* n_ops,
+                               int32_t* perm_out) {
+  if (n < 2 || n_gates < 0 || max_ops < 0 || !n_ops || (n_gates > 0 && (!qa || !qb)))
+    return fail(NZE_EINVAL, "bad routing arguments");
+  for (int g = 0; g < n_gates; ++g)
+    if (qa[g] < 0 || qa[g] >= n || qb[g] < 0 || qb[g] >= n || qa[g] == qb[g])
+      return fail(NZE_EINVAL, "gate qubits out of range or equal");
+  const bool write = op_site && op_gate && op_flip;
+  std::vector<int> pos(n), at(n);
+  for (int q = 0; q < n; ++q) pos[q] = at[q] = q;
+  int64_t k = 0;
+  auto emit = [&](int site, int gate, int flip) {
+    if (write && k < max_ops) {
+      op_site[k] = site;
+      op_gate[k] = gate;
+      op_flip[k] = static_cast<uint8_t>(flip);
+    }
+    ++k;
+  };
+  for (int g = 0; g < n_gates; ++g) {
+    const int a = qa[g], b = qb[g];
+    // the second qubit walks towards the first, one exchange per step
+    while (std::abs(pos[a] - pos[b]) > 1) {
+      const int sb = pos[b];
+      const int s = pos[a] > sb ? sb : sb - 1;
+      emit(s, -1, 0);
+      const int x = at[s], y = at[s + 1];
+      at[s] = y;
+      at[s + 1] = x;
+      pos[y] = s;
+      pos[x] = s + 1;
+    }
+    emit(std::min(pos[a], pos[b]), g, pos[a] > pos[b] ? 1 : 0);
+  }
+  if (k > INT32_MAX) return fail(NZE_EINVAL, "routed sequence too long");
+  *n_ops = static_cast<int32_t>(k);
+  if (perm_out)
+    for (int q = 0; q < n; ++q) perm_out[q] = pos[q];
+  if (write && k > max_ops) return fail(NZE_ENOMEM, "max_ops too small for the routed sequence");
   return NZE_OK;
 }
 

@@ -90,6 +90,10 @@ def lib():
                                      c_double_p, ctypes.c_double, ctypes.c_int32,
                                      ctypes.c_int32, c_double_p]
     L.nze_ptm_compose.argtypes = [c_double_p, c_double_p, c_double_p]
+    L.nze_ptm_swap_qubits.argtypes = [c_double_p, c_double_p]
+    L.nze_route_chain.argtypes = [ctypes.c_int32, ctypes.c_int32, c_int32_p, c_int32_p,
+                                  ctypes.c_int32, c_int32_p, c_int32_p,
+                                  ctypes.POINTER(ctypes.c_uint8), c_int32_p, c_int32_p]
     L.mpo_footprint.argtypes = [ctypes.POINTER(MpoConfig)]
     L.mpo_footprint.restype = ctypes.c_size_t
     L.mpo_init.argtypes = [ctypes.POINTER(ctypes.c_void_p),
@@ -214,6 +218,82 @@ def ptm_compose(first, second):
     b = np.ascontiguousarray(second, dtype=np.float64)
     out = np.empty((16, 16))
     _check(lib().nze_ptm_compose(_dp(a), _dp(b), _dp(out)))
+    return out
+
+
+def ptm_swap_qubits(ptm16):
+    """The PTM with its two qubits exchanged (nze_ptm_swap_qubits)."""
+    a = np.ascontiguousarray(ptm16, dtype=np.float64)
+    out = np.empty((16, 16))
+    _check(lib().nze_ptm_swap_qubits(_dp(a), _dp(out)))
+    return out
+
+
+SWAP_U = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]],
+                  dtype=np.complex128)
+
+
+def route_chain(n, pairs):
+    """nze_route_chain: ops [(site, gate index or -1 for a SWAP, flip)] of
+    the gates on logical qubit pairs routed onto the chain, and the final
+    chain site of each logical qubit."""
+    qa = np.ascontiguousarray([a for a, _ in pairs], dtype=np.int32)
+    qb = np.ascontiguousarray([b for _, b in pairs], dtype=np.int32)
+    cnt = ctypes.c_int32()
+    perm = np.empty(n, dtype=np.int32)
+    i32 = lambda a: a.ctypes.data_as(c_int32_p)
+    _check(lib().nze_route_chain(n, len(pairs), i32(qa), i32(qb), 0, None, None, None,
+                                 ctypes.byref(cnt), None))
+    k = cnt.value
+    site = np.empty(k, dtype=np.int32)
+    gate = np.empty(k, dtype=np.int32)
+    flip = np.empty(k, dtype=np.uint8)
+    _check(lib().nze_route_chain(n, len(pairs), i32(qa), i32(qb), k, i32(site), i32(gate),
+                                 flip.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                 ctypes.byref(cnt), i32(perm)))
+    return list(zip(site.tolist(), gate.tolist(), flip.tolist())), perm
+
+
+def routed_layers(n, gates, noise, factors):
+    """Gates (a, b, U) on logical qubit pairs as chain layers for
+    MPO.apply_layer: the routed ops in order, consecutive ops on disjoint
+    pairs grouped into one layer.  SWAPs are noiseless; a gate whose first
+    qubit lands on the right of its pair takes the exchanged PTM.  Returns
+    (layers as (left_sites, ptms[L][k][16][16]), final chain site of each
+    logical qubit)."""
+    ops, perm = route_chain(n, [(a, b) for a, b, _ in gates])
+    swap = build_ptm(SWAP_U)
+    layers, cur, used = [], [], set()
+
+    def flush():
+        if cur:
+            cur.sort(key=lambda o: o[0])
+            ptms = np.empty((len(factors), len(cur), 16, 16))
+            for j, c in enumerate(factors):
+                for i, (s, g, f) in enumerate(cur):
+                    if g < 0:
+                        ptms[j, i] = swap
+                    else:
+                        r = build_ptm(gates[g][2], noise, c)
+                        ptms[j, i] = ptm_swap_qubits(r) if f else r
+            layers.append(([o[0] for o in cur], ptms))
+        cur.clear()
+        used.clear()
+
+    for op in ops:
+        if op[0] in used or op[0] + 1 in used:
+            flush()
+        cur.append(op)
+        used.update((op[0], op[0] + 1))
+    flush()
+    return layers, perm
+
+
+def permute_paulis(paulis, perm):
+    """A Pauli string on logical qubits as the string on chain sites."""
+    out = np.zeros(len(paulis), dtype=np.uint8)
+    for q, p in enumerate(paulis):
+        out[perm[q]] = p
     return out
 
 
