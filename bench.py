@@ -173,6 +173,51 @@ def saturated_batches(nze, workloads, batches, first=6, timed=2):
     return out
 
 
+def lattice_run(nze, workloads, rows, cols, rounds, chi, levels=8, seed=0):
+    """A rows x cols lattice with open boundaries (qubits numbered
+    column-major), `rounds` rounds of one Haar SU(4) gate per edge, routed
+    onto the chain with noiseless SWAPs (layout restored after every gate) and
+    run at `levels` depolarizing levels (1..16) x 1e-3 in mixed precision.
+    Reports logical gates and chain updates (gates + SWAPs) per second of the
+    layer launches."""
+    import torch
+    rng = np.random.default_rng(seed)
+    q = lambda r, c: c * rows + r
+    edges = []
+    for c in range(cols):
+        for r in range(rows):
+            if r + 1 < rows:
+                edges.append((q(r, c), q(r + 1, c)))
+            if c + 1 < cols:
+                edges.append((q(r, c), q(r, c + 1)))
+    gates = [(a, b, workloads.haar_su4(rng)) for _ in range(rounds) for a, b in edges]
+    n = rows * cols
+    factors = list(np.linspace(1.0, 16.0, levels))
+    layers, perm = nze.routed_layers(n, gates, {"dep": 1e-3}, factors, restore=True)
+    ops = sum(len(ls) for ls, _ in layers)
+    m = nze.MPO(n, chi, levels, nze.NZE_MIXED)
+    try:
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for ls, ptms in layers:
+            m.apply_layer(ls, ptms)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        st, bonds = m.stats()
+    finally:
+        m.close()
+    return {"lattice": f"{rows}x{cols}", "rounds": rounds, "chi": chi, "levels": levels,
+            "logical_gates": len(gates), "chain_ops": ops, "swaps": ops - len(gates),
+            "layer_launches": len(layers), "kernel_ms": ms,
+            "logical_gates_per_s": 1e3 * len(gates) * levels / ms,
+            "chain_updates_per_s": 1e3 * ops * levels / ms,
+            "fidelity_min": float(min(x["fidelity"] for x in st))}
+
+
 def cpu_baseline(w, layers, timed_layer=5, budget_s=40.0):
     """The oracle on noise level 1: evolve the first layers (bonds grow to
     chi), then time one layer whose bonds are saturated."""
@@ -329,6 +374,8 @@ def main():
     ap.add_argument("--saturated-batches", default="1,8,32,64",
                     help="batch sizes of the saturated-update microbenchmark "
                          "(comma list; empty to skip)")
+    ap.add_argument("--lattice", default="",
+                    help="also run a routed 2D lattice: ROWSxCOLSxROUNDS (e.g. 2x25x8)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many MiB device-to-device five times "
                          "(calibrates the HBM byte counters)")
@@ -443,6 +490,12 @@ def main():
                 nze, workloads, [int(b) for b in args.saturated_batches.split(",")])
         except Exception as e:  # noqa: BLE001
             out["saturated_batch"] = {"error": repr(e)}
+    if args.lattice:
+        r, c, k = (int(x) for x in args.lattice.split("x"))
+        try:
+            out["lattice_2d"] = lattice_run(nze, workloads, r, c, k, w.chi)
+        except Exception as e:  # noqa: BLE001
+            out["lattice_2d"] = {"error": repr(e)}
     if not args.no_extrapolation_error:
         out["extrapolation_error_n8"] = extrapolation_error(nze, workloads)
     if not args.no_cpu_baseline:

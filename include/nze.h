@@ -123,11 +123,13 @@ int nze_ptm_swap_qubits(const double* ptm_in, double* ptm_out);
  * lattices laid out along the chain (Sec. 3 orders the lattice qubits
  * column- or row-major).  Logical qubit q starts on chain site q; for each
  * input gate g, in order, the qubit qb[g] is moved towards qa[g] by SWAPs
- * until the two are neighbours, then the gate is applied; qubits are not
- * moved back.
+ * until the two are neighbours, then the gate is applied, then (restore != 0)
+ * the same SWAPs in reverse order move it back.
  *   n        : chain length (>= 2); n_gates: input gates (>= 0).
  *   qa, qb   : n_gates logical qubit pairs, 0 <= qa, qb < n, qa != qb
  *              (qa is the first qubit of the gate's 4x4 matrix).
+ *   restore  : nonzero to restore the layout after every gate (the final
+ *              permutation is then the identity).
  *   max_ops  : capacity of the three output arrays.
  *   op_site  : left chain site s of each op, acting on sites (s, s+1).
  *   op_gate  : input gate index of the op, or -1 for a SWAP.
@@ -140,7 +142,7 @@ int nze_ptm_swap_qubits(const double* ptm_in, double* ptm_out);
  * Host-only.  Errors: NZE_EINVAL (bad sizes or qubits), NZE_ENOMEM (op
  * arrays given and max_ops < n_ops). */
 int nze_route_chain(int32_t n, int32_t n_gates, const int32_t* qa, const int32_t* qb,
-                    int32_t max_ops, int32_t* op_site, int32_t* op_gate,
+                    int32_t restore, int32_t max_ops, int32_t* op_site, int32_t* op_gate,
                     uint8_t* op_flip, int32_t* n_ops, int32_t* perm_out);
 
 /* ------------------------------------------------------------ MPO handle */

@@ -274,9 +274,9 @@ extern "C" int nze_ptm_swap_qubits(const double* ptm_in, double* ptm_out) {
 }
 
 extern "C" int nze_route_chain(int32_t n, int32_t n_gates, const int32_t* qa,
-                               const int32_t* qb, int32_t max_ops, int32_t* op_site,
-                               int32_t* op_gate, uint8_t* op_flip, int32_t* n_ops,
-                               int32_t* perm_out) {
+                               const int32_t* qb, int32_t restore, int32_t max_ops,
+                               int32_t* op_site, int32_t* op_gate, uint8_t* op_flip,
+                               int32_t* n_ops, int32_t* perm_out) {
   if (n < 2 || n_gates < 0 || max_ops < 0 || !n_ops || (n_gates > 0 && (!qa || !qb)))
     return fail(NZE_EINVAL, "bad routing arguments");
   for (int g = 0; g < n_gates; ++g)
@@ -294,20 +294,29 @@ extern "C" int nze_route_chain(int32_t n, int32_t n_gates, const int32_t* qa,
     }
     ++k;
   };
+  auto exchange = [&](int s) {
+    emit(s, -1, 0);
+    const int x = at[s], y = at[s + 1];
+    at[s] = y;
+    at[s + 1] = x;
+    pos[y] = s;
+    pos[x] = s + 1;
+  };
+  std::vector<int> walked;
   for (int g = 0; g < n_gates; ++g) {
     const int a = qa[g], b = qb[g];
     // the second qubit walks towards the first, one exchange per step
+    walked.clear();
     while (std::abs(pos[a] - pos[b]) > 1) {
       const int sb = pos[b];
       const int s = pos[a] > sb ? sb : sb - 1;
-      emit(s, -1, 0);
-      const int x = at[s], y = at[s + 1];
-      at[s] = y;
-      at[s + 1] = x;
-      pos[y] = s;
-      pos[x] = s + 1;
+      exchange(s);
+      walked.push_back(s);
     }
     emit(std::min(pos[a], pos[b]), g, pos[a] > pos[b] ? 1 : 0);
+    // and walks back (layout unchanged) when asked to
+    if (restore)
+      for (int i = static_cast<int>(walked.size()) - 1; i >= 0; --i) exchange(walked[i]);
   }
   if (k > INT32_MAX) return fail(NZE_EINVAL, "routed sequence too long");
   *n_ops = static_cast<int32_t>(k);

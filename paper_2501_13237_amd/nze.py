@@ -80,6 +80,10 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "paper_2501_13237_amd.build.build()")
+    # torch first: it brings its own HIP runtime, and the library must bind
+    # to that same runtime (loaded the other way round, two runtimes open the
+    # device and the second finds none)
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     L.nze_build_ptm.argtypes = [c_double_p, c_double_p,
                                 ctypes.POINTER(NzeNoise), ctypes.c_double,
@@ -92,7 +96,7 @@ def lib():
     L.nze_ptm_compose.argtypes = [c_double_p, c_double_p, c_double_p]
     L.nze_ptm_swap_qubits.argtypes = [c_double_p, c_double_p]
     L.nze_route_chain.argtypes = [ctypes.c_int32, ctypes.c_int32, c_int32_p, c_int32_p,
-                                  ctypes.c_int32, c_int32_p, c_int32_p,
+                                  ctypes.c_int32, ctypes.c_int32, c_int32_p, c_int32_p,
                                   ctypes.POINTER(ctypes.c_uint8), c_int32_p, c_int32_p]
     L.mpo_footprint.argtypes = [ctypes.POINTER(MpoConfig)]
     L.mpo_footprint.restype = ctypes.c_size_t
@@ -233,35 +237,37 @@ SWAP_U = np.array([[1, 0, 0, 0], [0, 0, 1, 0], [0, 1, 0, 0], [0, 0, 0, 1]],
                   dtype=np.complex128)
 
 
-def route_chain(n, pairs):
+def route_chain(n, pairs, restore=False):
     """nze_route_chain: ops [(site, gate index or -1 for a SWAP, flip)] of
-    the gates on logical qubit pairs routed onto the chain, and the final
-    chain site of each logical qubit."""
+    the gates on logical qubit pairs routed onto the chain (with the layout
+    restored after every gate when ``restore``), and the final chain site of
+    each logical qubit."""
     qa = np.ascontiguousarray([a for a, _ in pairs], dtype=np.int32)
     qb = np.ascontiguousarray([b for _, b in pairs], dtype=np.int32)
     cnt = ctypes.c_int32()
     perm = np.empty(n, dtype=np.int32)
     i32 = lambda a: a.ctypes.data_as(c_int32_p)
-    _check(lib().nze_route_chain(n, len(pairs), i32(qa), i32(qb), 0, None, None, None,
-                                 ctypes.byref(cnt), None))
+    _check(lib().nze_route_chain(n, len(pairs), i32(qa), i32(qb), int(bool(restore)), 0,
+                                 None, None, None, ctypes.byref(cnt), None))
     k = cnt.value
     site = np.empty(k, dtype=np.int32)
     gate = np.empty(k, dtype=np.int32)
     flip = np.empty(k, dtype=np.uint8)
-    _check(lib().nze_route_chain(n, len(pairs), i32(qa), i32(qb), k, i32(site), i32(gate),
+    _check(lib().nze_route_chain(n, len(pairs), i32(qa), i32(qb), int(bool(restore)), k,
+                                 i32(site), i32(gate),
                                  flip.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                                  ctypes.byref(cnt), i32(perm)))
     return list(zip(site.tolist(), gate.tolist(), flip.tolist())), perm
 
 
-def routed_layers(n, gates, noise, factors):
+def routed_layers(n, gates, noise, factors, restore=False):
     """Gates (a, b, U) on logical qubit pairs as chain layers for
     MPO.apply_layer: the routed ops in order, consecutive ops on disjoint
     pairs grouped into one layer.  SWAPs are noiseless; a gate whose first
     qubit lands on the right of its pair takes the exchanged PTM.  Returns
     (layers as (left_sites, ptms[L][k][16][16]), final chain site of each
     logical qubit)."""
-    ops, perm = route_chain(n, [(a, b) for a, b, _ in gates])
+    ops, perm = route_chain(n, [(a, b) for a, b, _ in gates], restore)
     swap = build_ptm(SWAP_U)
     layers, cur, used = [], [], set()
 

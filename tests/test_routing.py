@@ -41,14 +41,15 @@ def lattice_circuit(rows, cols, steps, seed, periodic=True):
     return gates
 
 
-def test_route_chain_ops_are_adjacent_and_oriented():
+@pytest.mark.parametrize("restore", [False, True])
+def test_route_chain_ops_are_adjacent_and_oriented(restore):
     rng = np.random.default_rng(3)
     for n in (2, 3, 7, 12):
         pairs = []
         for _ in range(40):
             a, b = rng.choice(n, size=2, replace=False)
             pairs.append((int(a), int(b)))
-        ops, perm = nze.route_chain(n, pairs)
+        ops, perm = nze.route_chain(n, pairs, restore)
         at = list(range(n))
         seen = 0
         for s, g, f in ops:
@@ -62,6 +63,8 @@ def test_route_chain_ops_are_adjacent_and_oriented():
             seen += 1
         assert seen == len(pairs)
         assert [at.index(q) for q in range(n)] == list(perm)
+        if restore:
+            assert list(perm) == list(range(n))
 
 
 def test_route_chain_rejects_bad_input():
@@ -84,10 +87,10 @@ def test_ptm_swap_qubits_is_the_exchanged_gate(noise):
     assert np.max(np.abs(nze.ptm_swap_qubits(got) - nze.build_ptm(U, noise))) == 0.0
 
 
-def oracle_routed(n, gates, noise, chi):
+def oracle_routed(n, gates, noise, chi, restore=False):
     """The oracle MPO on the routed op sequence (oracle PTMs; noiseless
     SWAPs), with the ops grouped as the binding groups them."""
-    ops, perm = nze.route_chain(n, [(a, b) for a, b, _ in gates])
+    ops, perm = nze.route_chain(n, [(a, b) for a, b, _ in gates], restore)
     nz = ptm.Noise(**noise)
     m = ompo.PauliMPO(n, chi)
     cur = []
@@ -116,12 +119,12 @@ def oracle_routed(n, gates, noise, chi):
     return m, perm
 
 
-@pytest.mark.parametrize("rows,cols", [(2, 3), (3, 2)])
-def test_routed_lattice_circuit_matches_dense(rows, cols):
+@pytest.mark.parametrize("rows,cols,restore", [(2, 3, False), (3, 2, False), (2, 3, True)])
+def test_routed_lattice_circuit_matches_dense(rows, cols, restore):
     n = rows * cols
     gates = lattice_circuit(rows, cols, 2, seed=rows * 10 + cols)
     noise = {"dep": 0.01, "ad": 0.005}
-    m, perm = oracle_routed(n, gates, noise, chi=4 ** (n // 2))
+    m, perm = oracle_routed(n, gates, noise, chi=4 ** (n // 2), restore=restore)
     rho = dense.product_state([0] * n)
     for a, b, U in gates:
         rho = dense.apply_noisy_gate_pair(rho, n, a, b, U, ptm.Noise(**noise))
@@ -147,7 +150,7 @@ def test_routed_lattice_gpu_matches_dense(precision, tol):
     noise = {"dep": 1e-3}
     factors = [1.0, 4.0]
     print(f"routed lattice {rows}x{cols} precision={precision}", flush=True)
-    layers, perm = nze.routed_layers(n, gates, noise, factors)
+    layers, perm = nze.routed_layers(n, gates, noise, factors, restore=True)
     m = nze.MPO(n, 256, len(factors), precision)
     try:
         for ls, ptms in layers:
