@@ -94,20 +94,45 @@ template <typename T> __device__ inline int mrow(int kq, int r);
 template <> __device__ inline int mrow<float>(int kq, int r) { return 4 * kq + r; }
 template <> __device__ inline int mrow<double>(int kq, int r) { return kq + 4 * r; }
 
+// Row data lives in device (global) memory, but its pointers come out of the
+// slot records as generic pointers; these accessors cast them to the global
+// address space so that the accesses are global, not flat, instructions
+// (flat accesses also count against the LDS wait counter, so every LDS wait
+// of the pair phases would wait for them too).
+typedef float nze_v4f __attribute__((ext_vector_type(4)));
+typedef float nze_v2f __attribute__((ext_vector_type(2)));
+typedef double nze_v2d __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const nze_v4f g_cv4f;
+typedef __attribute__((address_space(1))) const nze_v2d g_cv2d;
+typedef __attribute__((address_space(1))) nze_v2f g_v2f;
+typedef __attribute__((address_space(1))) nze_v2d g_v2d;
+
+template <typename T>
+__device__ inline T load1(const T* p) {
+  return *(__attribute__((address_space(1))) const T*)p;
+}
+template <typename T>
+__device__ inline void store1(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
 __device__ inline void load4(const float* p, float v[4]) {
-  const float4 x = *reinterpret_cast<const float4*>(p);
+  const nze_v4f x = *(g_cv4f*)p;
   v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
 }
 __device__ inline void load4(const double* p, double v[4]) {
-  const double2 a = *reinterpret_cast<const double2*>(p);
-  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  const nze_v2d a = *(g_cv2d*)p;
+  const nze_v2d b = *(g_cv2d*)(p + 2);
   v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
 }
 __device__ inline void store2(float* p, float a, float b) {
-  *reinterpret_cast<float2*>(p) = make_float2(a, b);
+  nze_v2f x;
+  x.x = a; x.y = b;
+  *(g_v2f*)p = x;
 }
 __device__ inline void store2(double* p, double a, double b) {
-  *reinterpret_cast<double2*>(p) = make_double2(a, b);
+  nze_v2d x;
+  x.x = a; x.y = b;
+  *(g_v2d*)p = x;
 }
 
 __device__ inline double wave_sum(double v) {

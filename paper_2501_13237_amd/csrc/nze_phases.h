@@ -430,7 +430,7 @@ __device__ void pair_rotate(T* M, int ld, int ncols, const PairLds& L) {
       const bool cok = c < ncols;
 #pragma unroll
       for (int s = 0; s < 8; ++s)
-        xb[h][s] = (cok && src[s] >= 0) ? M[(size_t)src[s] * ld + c] : T(0);
+        xb[h][s] = (cok && src[s] >= 0) ? load1(M + (size_t)src[s] * ld + c) : T(0);
     }
 #pragma unroll
     for (int h = 0; h < NCH; ++h) {
@@ -444,8 +444,8 @@ __device__ void pair_rotate(T* M, int ld, int ncols, const PairLds& L) {
       if (c < ncols) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          if (dst0[r] >= 0) M[(size_t)dst0[r] * ld + c] = d0[r];
-          if (dst1[r] >= 0) M[(size_t)dst1[r] * ld + c] = d1[r];
+          if (dst0[r] >= 0) store1(M + (size_t)dst0[r] * ld + c, T(d0[r]));
+          if (dst1[r] >= 0) store1(M + (size_t)dst1[r] * ld + c, T(d1[r]));
         }
       }
     }
@@ -466,7 +466,7 @@ __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
   if (tid < 32) {
     const int blk = tid < 16 ? I : J;
     const int r = blk * BW + (tid & 15);
-    L.rows[tid] = (blk < nb && r < R) ? order[r] : -1;
+    L.rows[tid] = (blk < nb && r < R) ? load1(order + r) : -1;
   }
   if (tid == 0) L.flag[1] = 0;
   __syncthreads();
@@ -510,7 +510,7 @@ __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
   // the last round visits every block once: the diagonal of the pair's Gram
   // after the visit (Q^T G Q when it rotated) gives the squared row norms
   // that order the next sweep, without a pass over X
-  if (last_round && tid < 32 && L.rows[tid] >= 0) s.norms[L.rows[tid]] = Gfin[tid * GLD + tid];
+  if (last_round && tid < 32 && L.rows[tid] >= 0) store1(s.norms + L.rows[tid], Gfin[tid * GLD + tid]);
   blocks_release(grp, verX, I, J);
   // accumulator rows: previous visits of both blocks first, in visit order
   if (!blocks_wait(grp, verW, I, J, target)) return false;
@@ -528,7 +528,10 @@ __device__ void phase_norms(const Slot& s, const T* X, int R, int C, int g,
   for (int r = g * 4 + w; r < R; r += 4 * G) {
     double acc = 0.0;
     const T* x = X + (size_t)r * C;
-    for (int c = lane; c < C; c += 64) acc += double(x[c]) * double(x[c]);
+    for (int c = lane; c < C; c += 64) {
+      const double v = double(load1(x + c));
+      acc += v * v;
+    }
     acc = wave_sum(acc);
     if (lane == 0) s.norms[r] = acc;
   }
