@@ -686,6 +686,15 @@ int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& 
       --want_tot;
     }
   }
+  // A batch that asks for at most half of the CUs gets its groups doubled
+  // (still one workgroup per CU): consecutive Jacobi rounds then alternate
+  // between two sets of workgroups, and the accumulator rotation of one round
+  // runs beside the next round's data visits.  Two such workgroups sharing a
+  // CU gain nothing (measured), hence only on idle CUs.
+  if (!x2 && want_tot * 2 <= (long long)di.cus && occ == 1) {
+    for (int& x : gm) x *= 2;
+    want_tot *= 2;
+  }
   const bool uniform = std::all_of(gm.begin(), gm.end(), [&](int x) { return x == gm[0]; });
   const int G = gm[0];
   // XCD-local groups: every XCD hosts nmpo / 8 whole MPOs (the grid of
