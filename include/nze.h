@@ -337,7 +337,7 @@ int nze_fidelity_extrapolate(int32_t n_pts, const double* value,
  * are admitted in arrival order when their mpo_footprint fits into free
  * space of a caller-owned device arena and a slot is free; admitted jobs stay
  * resident, and every nze_server_step advances all resident jobs by one layer
- * in shared persistent launches (at most 128 MPOs per launch).  A job that has
+ * in shared persistent launches (at most 256 MPOs per launch).  A job that has
  * run all its layers is read out (mpo_expect) and its memory is released.
  * Because every MPO is computed by its own workgroups with the same
  * arithmetic, a job's results do not depend on which jobs share its launches.
