@@ -171,3 +171,24 @@ def test_routed_lattice_gpu_matches_dense(precision, tol):
         print(f"  level {j}: max|dO| = {err:.2e}, F = {fid[j]:.15f}", flush=True)
         assert err < tol
         assert abs(fid[j] - 1.0) < tol
+
+
+def test_route_chain_swap_counts():
+    # with the layout restored after every gate, a gate at chain distance d
+    # costs 2 (d - 1) SWAPs; nearest-neighbour gates (a brickwork) cost none
+    rng = np.random.default_rng(5)
+    n = 9
+    pairs = [tuple(int(x) for x in rng.choice(n, size=2, replace=False)) for _ in range(30)]
+    ops, perm = nze.route_chain(n, pairs, restore=True)
+    assert sum(1 for _, g, _ in ops if g < 0) == sum(2 * (abs(a - b) - 1) for a, b in pairs)
+    assert list(perm) == list(range(n))
+    brick = [(k, k + 1) for t in range(4) for k in range(t % 2, n - 1, 2)]
+    for restore in (False, True):
+        ops, perm = nze.route_chain(n, brick, restore)
+        assert all(g >= 0 for _, g, _ in ops) and len(ops) == len(brick)
+
+
+def test_permute_paulis_moves_each_letter_to_its_site():
+    perm = np.array([2, 0, 3, 1])
+    got = nze.permute_paulis(np.array([1, 2, 3, 0], dtype=np.uint8), perm)
+    assert list(got) == [2, 0, 1, 3]
