@@ -458,7 +458,7 @@ __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
                             int J, int nb, int sw, double F2, double* smem,
                             bool timed, const int* order, Group& grp,
                             int* verX, int* verW, int target, bool last_round,
-                            bool cross_only) {
+                            bool cross_only, bool forced) {
   const PairLds L = pair_lds(smem);
   const int tid = threadIdx.x;
   PhaseClock clk(timed && s.prof != nullptr);
@@ -472,31 +472,34 @@ __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
   __syncthreads();
   pair_gram<T>(X, C, C, L);
   clk.lap(s.prof, PF_GRAM);
-  // convergence test: |g_uv| > tol sqrt(g_uu g_vv) + tol_abs sqrt(F2 max);
-  // tol is raised to the rounding level of a length-C dot product of the path
-  const double eps = sizeof(T) == 4 ? 5.96e-8 : 1.11e-16;
-  const double tol = fmax(s.tol_rel, 8.0 * sqrt((double)C) * eps);
-  const double ratio_abs = s.tol_abs / tol;
-  float worst = 0.f;   // largest |g_uv| / (sqrt(g_uu g_vv) + ratio_abs sqrt(F2 max))
-  for (int e = tid; e < 1024; e += NT) {
-    const int u = e >> 5, v = e & 31;
-    if (v <= u) continue;
-    const double guu = L.Gs[u * GLD + u], gvv = L.Gs[v * GLD + v];
-    const double guv = fabs(L.Gs[u * GLD + v]);
-    // a tolerance test: hardware root and reciprocal (~1e-7 relative) suffice
-    const double den = __builtin_amdgcn_sqrt(guu * gvv) +
-                       ratio_abs * __builtin_amdgcn_sqrt(F2 * fmax(guu, gvv));
-    const double q = den > 0.0 ? guv * __builtin_amdgcn_rcp(den) : (guv > 0.0 ? 1.0 : 0.0);
-    worst = fmaxf(worst, (q == q) ? float(q) : 1.0f);
+  int go = 1;
+  if (!forced) {
+    // convergence test: |g_uv| > tol sqrt(g_uu g_vv) + tol_abs sqrt(F2 max);
+    // tol is raised to the rounding level of a length-C dot product of the path
+    const double eps = sizeof(T) == 4 ? 5.96e-8 : 1.11e-16;
+    const double tol = fmax(s.tol_rel, 8.0 * sqrt((double)C) * eps);
+    const double ratio_abs = s.tol_abs / tol;
+    float worst = 0.f;   // largest |g_uv| / (sqrt(g_uu g_vv) + ratio_abs sqrt(F2 max))
+    for (int e = tid; e < 1024; e += NT) {
+      const int u = e >> 5, v = e & 31;
+      if (v <= u) continue;
+      const double guu = L.Gs[u * GLD + u], gvv = L.Gs[v * GLD + v];
+      const double guv = fabs(L.Gs[u * GLD + v]);
+      // a tolerance test: hardware root and reciprocal (~1e-7 relative) suffice
+      const double den = __builtin_amdgcn_sqrt(guu * gvv) +
+                         ratio_abs * __builtin_amdgcn_sqrt(F2 * fmax(guu, gvv));
+      const double q = den > 0.0 ? guv * __builtin_amdgcn_rcp(den) : (guv > 0.0 ? 1.0 : 0.0);
+      worst = fmaxf(worst, (q == q) ? float(q) : 1.0f);
+    }
+    for (int o = 32; o > 0; o >>= 1) worst = fmaxf(worst, __shfl_xor(worst, o, 64));
+    const int need = worst > float(tol);
+    if ((tid & 63) == 0 && worst > 0.f)
+      atomicMax(&s.ctr[CT_OFFMAX], __float_as_int(worst));
+    if (need) L.flag[1] = 1;
+    __syncthreads();
+    go = L.flag[1];
+    __syncthreads();
   }
-  for (int o = 32; o > 0; o >>= 1) worst = fmaxf(worst, __shfl_xor(worst, o, 64));
-  const int need = worst > float(tol);
-  if ((tid & 63) == 0 && worst > 0.f)
-    atomicMax(&s.ctr[CT_OFFMAX], __float_as_int(worst));
-  if (need) L.flag[1] = 1;
-  __syncthreads();
-  const int go = L.flag[1];
-  __syncthreads();
   clk.lap(s.prof, PF_CHECK);
   const double* Gfin = L.Gs;
   if (go) {
@@ -618,10 +621,14 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
     // sweep, so pairs left inside a block meet as cross pairs later; every
     // later sweep runs full inner sweeps, which polish all pairs.
     bool cross_only = false;
-    if (nb >= 64 && sw < 6)
+    if (nb >= 64 && sw < 8)
       cross_only = sw == 0 ||
                    __hip_atomic_load(&s.ctr[CT_ROT + sw - 1], __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT) == rounds * npair;
+    // after the first sweep such a sweep rotates every pair without the
+    // convergence test (the sweep before rotated every pair; the later full
+    // sweeps test and polish all of them)
+    const bool forced = cross_only && sw > 0;
     // visit v = t npair + q (pair q of round t) belongs to workgroup v mod G;
     // each workgroup takes its visits in increasing order, and a visit waits
     // only for the previous round's visits of its two blocks, so rounds
@@ -642,7 +649,7 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
           }
         }
         if (!jacobi_pair<T, VEC>(s, X, W, R, C, I, J, nb, sw, F2, smem, g == 0, s.perm,
-                            grp, ver, wver, base + t, t == rounds - 1, cross_only))
+                            grp, ver, wver, base + t, t == rounds - 1, cross_only, forced))
           return false;
       }
     }
