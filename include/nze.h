@@ -150,7 +150,7 @@ typedef struct mpo_handle mpo_t;
 
 typedef struct mpo_config {
   int32_t n;           /* qubits on the open chain, 2 <= n <= 4096            */
-  int32_t chi_max;     /* maximum bond dimension D (Sec. 2.1.1), 1..1024       */
+  int32_t chi_max;     /* maximum bond dimension D (Sec. 2.1.1), 1..512        */
   int32_t n_levels;    /* L independent MPOs (one per noise level), >= 1      */
   int32_t precision;   /* NZE_FP64 or NZE_MIXED                               */
   double trunc_tol;    /* tau: drop s_i <= tau * s_1 (numerical zeros);
@@ -159,11 +159,13 @@ typedef struct mpo_config {
                           is dropped whole); 0 -> 1e-10 (FP64) / 1e-5 (mixed)*/
   double jacobi_tol;   /* relative off-diagonal threshold of the one-sided
                           Jacobi SVD: rows u, v count as orthogonal when
-                          |<x_u,x_v>| <= tol |x_u||x_v| + tol_abs |X| |x_max|;
-                          tol is raised to at least 8 sqrt(C) eps of the path
-                          (C = row length);
-                          0 -> 1e-13 (FP64) / 2e-6 (mixed);
-                          tol_abs is 1e-15 (FP64) / 1e-6 (mixed)             */
+                          |<x_u,x_v>| <= tol |x_u||x_v| + jacobi_abs |X| |x_max|
+                          (|X| Frobenius norm of the block, x_max the longer
+                          of the two rows); tol is raised to at least
+                          8 sqrt(C) eps (FP64, C = row length) or eps (mixed);
+                          0 -> 1e-13 (FP64) / 1e-7 (mixed)                    */
+  double jacobi_abs;   /* absolute part of that threshold;
+                          0 -> 1e-15 (FP64) / 1e-8 (mixed)                    */
   int32_t max_sweeps;  /* Jacobi sweep cap (<= 40); 0 -> 40                   */
   int32_t block;       /* Jacobi row-block width b (pairs are 2b rows);
                           0 -> chosen by the built-in tuner                   */

@@ -183,10 +183,24 @@ __device__ void phase_theta(const Slot& s, int k, bool ltr, const double* R,
 
 // --------------------------------------------------------- Jacobi phase
 
+// Relative off-diagonal threshold of the Jacobi convergence test on rows of
+// length C.  Float64: at least 8 sqrt(C) eps, the worst-case rounding of a
+// length-C dot product.  Float32 rows: at least eps itself.  Rounding of the
+// float32 rows and of the MFMA Gram leaves a relative coupling of about
+// eps / sqrt(C) between orthogonal rows, far below the worst-case bound, and a
+// threshold at that bound (8 sqrt(C) eps = 7.6e-6 at C = 256) leaves exactly
+// the near-degenerate pairs around a truncation cut unrotated: their mixing
+// angle tol / (2 relative gap) then decides which directions are kept.
+template <typename T>
+__device__ inline double jacobi_threshold(const Slot& s, int C) {
+  if (sizeof(T) == 4) return fmax(s.tol_rel, 5.96e-8);
+  return fmax(s.tol_rel, 8.0 * sqrt((double)C) * 1.11e-16);
+}
+
 // LDS layout of one pair step
 struct PairLds {
   double* Gp;     // [4][1024] per-wave partial Grams; during the inner solve
-                  // the second Gram buffer and each wave's (c, s) slots
+                  // the second Gram buffer
   double* Gs;     // [32][GLD]
   double* Qs;     // [32][GLD]
   int* rows;      // [32] global row of each pair row (-1 = none)
@@ -306,13 +320,16 @@ __device__ inline void sweep_pair32(int k, int st, int& p, int& q) {
 // One cyclic parallel Jacobi sweep on the 32x32 symmetric Gs (float64, LDS),
 // cross-block steps first (both blocks enter with nearly orthogonal rows
 // once a sweep has visited them, so the cross entries carry most of the
-// off-diagonal weight); Qs accumulates the rotations.  Lanes 0-15 of every
-// wave compute the step's rotations into the wave's own LDS slots, and G
-// ping-pongs between Gs and a second buffer (the dead Gram partials), so a
-// step needs one workgroup barrier.  Thread t owns the 2x2 block (pair t/16,
-// pair t%16) of G and rows 2(t/16), 2(t/16)+1 of Qs at pair t%16.  With
-// cross_only the sweep stops after the 16 cross-block steps.  Returns the
-// buffer that holds the rotated Gram Q^T G Q.
+// off-diagonal weight); Qs accumulates the rotations.  Thread t owns the 2x2
+// block (pair t/16, pair t%16) of G and rows 2(t/16), 2(t/16)+1 of Qs at pair
+// t%16, and computes the two rotations it needs itself from the step's
+// pivots: every LDS read of a step is issued at once, with no second round
+// trip to share the rotations, and the two rotation chains run side by side.
+// Threads that need the same rotation compute it from the same values with
+// the same instructions, so they agree bit for bit.  G ping-pongs between Gs
+// and a second buffer (the dead Gram partials): one workgroup barrier a
+// step.  With cross_only the sweep stops after the 16 cross-block steps.
+// Returns the buffer that holds the rotated Gram Q^T G Q.
 __device__ const double* inner_eigh(const PairLds& L, bool cross_only) {
   const int tid = threadIdx.x;
   for (int e = tid; e < 32 * 32; e += NT) {
@@ -325,37 +342,22 @@ __device__ const double* inner_eigh(const PairLds& L, bool cross_only) {
   const int P = tid >> 4, P2 = tid & 15;
   double* Ga = L.Gs;
   double* Gb = L.Gp;          // 32 x GLD, free once the Gram is reduced
-  double* csw = L.Gp + 2048 + 32 * (tid >> 6);   // this wave's (c, s) slots
   __syncthreads();
   const int nsteps = cross_only ? 16 : 31;
+  const int u0 = 2 * P;
   for (int st = 0; st < nsteps; ++st) {
     int p, q, p2, q2;
     sweep_pair32(P, st, p, q);
     sweep_pair32(P2, st, p2, q2);
-    // the sixteen rotations of the step are computed by lanes 0-15 of each
-    // wave (one dependent chain each) and shared inside the wave through its
-    // own LDS slots: a wave's LDS operations complete in order, so no
-    // workgroup barrier is needed
-    if ((tid & 63) < 16) {
-      const int k = tid & 15;
-      int a, b;
-      sweep_pair32(k, st, a, b);
-      double ct, stt;
-      jacobi_cs(Ga[a * GLD + a], Ga[b * GLD + b], Ga[a * GLD + b], floor_abs, ct, stt);
-      csw[k] = ct;
-      csw[16 + k] = stt;
-    }
-    // the thread's G and Q reads (the four Q entries are its own within the
-    // step)
-    const int u0 = 2 * P;
+    const double app = Ga[p * GLD + p], aqq = Ga[q * GLD + q], apq = Ga[p * GLD + q];
+    const double bpp = Ga[p2 * GLD + p2], bqq = Ga[q2 * GLD + q2], bpq = Ga[p2 * GLD + q2];
     const double g11 = Ga[p * GLD + p2], g12 = Ga[p * GLD + q2];
     const double g21 = Ga[q * GLD + p2], g22 = Ga[q * GLD + q2];
     const double qa = L.Qs[u0 * GLD + p2], qb = L.Qs[u0 * GLD + q2];
     const double qc = L.Qs[(u0 + 1) * GLD + p2], qd = L.Qs[(u0 + 1) * GLD + q2];
-    __builtin_amdgcn_s_waitcnt(0xc07f);          // lgkmcnt(0)
-    __builtin_amdgcn_wave_barrier();
-    asm volatile("" ::: "memory");
-    const double c = csw[P], sn = csw[16 + P], c2 = csw[P2], s2 = csw[16 + P2];
+    double c, sn, c2, s2;
+    jacobi_cs(app, aqq, apq, floor_abs, c, sn);
+    jacobi_cs(bpp, bqq, bpq, floor_abs, c2, s2);
     const double h11 = c * g11 - sn * g21, h12 = c * g12 - sn * g22;
     const double h21 = sn * g11 + c * g21, h22 = sn * g12 + c * g22;
     Gb[p * GLD + p2] = c2 * h11 - s2 * h12;
@@ -474,10 +476,8 @@ __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
   clk.lap(s.prof, PF_GRAM);
   int go = 1;
   if (!forced) {
-    // convergence test: |g_uv| > tol sqrt(g_uu g_vv) + tol_abs sqrt(F2 max);
-    // tol is raised to the rounding level of a length-C dot product of the path
-    const double eps = sizeof(T) == 4 ? 5.96e-8 : 1.11e-16;
-    const double tol = fmax(s.tol_rel, 8.0 * sqrt((double)C) * eps);
+    // convergence test: |g_uv| > tol sqrt(g_uu g_vv) + tol_abs sqrt(F2 max)
+    const double tol = jacobi_threshold<T>(s, C);
     const double ratio_abs = s.tol_abs / tol;
     float worst = 0.f;   // largest |g_uv| / (sqrt(g_uu g_vv) + ratio_abs sqrt(F2 max))
     for (int e = tid; e < 1024; e += NT) {
@@ -628,7 +628,9 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
     // after the first sweep such a sweep rotates every pair without the
     // convergence test (the sweep before rotated every pair; the later full
     // sweeps test and polish all of them)
-    const bool forced = cross_only && sw > 0;
+    // (never the last sweep the cap allows: that one measures the largest
+    // off-diagonal that decides between a benign cap and ERR_NOCONV)
+    const bool forced = cross_only && sw > 0 && sw + 1 < s.max_sweeps;
     // visit v = t npair + q (pair q of round t) belongs to workgroup v mod G;
     // each workgroup takes its visits in increasing order, and a visit waits
     // only for the previous round's visits of its two blocks, so rounds
@@ -668,8 +670,7 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
     if (sweeps > s.ctr[CT_MAXSW]) s.ctr[CT_MAXSW] = sweeps;
     if (!conv) {
       // the cap was reached: fine at the rounding floor, an error beyond it
-      const double eps = sizeof(T) == 4 ? 5.96e-8 : 1.11e-16;
-      const double tol = fmax(s.tol_rel, 8.0 * sqrt((double)C) * eps);
+      const double tol = jacobi_threshold<T>(s, C);
       const float worst = __int_as_float(s.ctr[CT_OFFMAX]);
       s.scal[SC_CAPQ] = fmax(s.scal[SC_CAPQ], double(worst) / tol);
       if (double(worst) > 1e3 * tol) s.ctr[CT_ERR] |= ERR_NOCONV;

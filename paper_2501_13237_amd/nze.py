@@ -31,7 +31,7 @@ class MpoConfig(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("chi_max", ctypes.c_int32),
                 ("n_levels", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("trunc_tol", ctypes.c_double), ("tie_tol", ctypes.c_double),
-                ("jacobi_tol", ctypes.c_double),
+                ("jacobi_tol", ctypes.c_double), ("jacobi_abs", ctypes.c_double),
                 ("max_sweeps", ctypes.c_int32), ("block", ctypes.c_int32)]
 
 
@@ -394,9 +394,10 @@ def kernel_rowortho(X, tol_rel, tol_abs, max_sweeps=40):
 
 
 def make_config(n, chi, levels, precision=NZE_FP64, trunc_tol=0.0,
-                tie_tol=0.0, jacobi_tol=0.0, max_sweeps=0, block=0):
+                tie_tol=0.0, jacobi_tol=0.0, jacobi_abs=0.0, max_sweeps=0,
+                block=0):
     return MpoConfig(n, chi, levels, precision, trunc_tol, tie_tol,
-                     jacobi_tol, max_sweeps, block)
+                     jacobi_tol, jacobi_abs, max_sweeps, block)
 
 
 def footprint(cfg):

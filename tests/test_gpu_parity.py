@@ -484,30 +484,26 @@ def test_eight_levels_one_launch_mixed_exact():
     _compare(n, layers, {"dep": 1e-3}, factors, 256, obs, nze.NZE_MIXED, MIXED_TOL)
 
 
-def test_mixed_truncated_error_bounded():
-    # Under truncation the mixed path's error is set by the cut gaps: a kept
-    # subspace whose relative gap g is below ~sqrt(m) 2^-24 is resolved only to
-    # about sqrt(m) 2^-24 / g (m = 4 chi rows).  This circuit's smallest gaps
-    # are 4.6e-6 (noise 1 x p) and 2.0e-5 (4 x p), so each level is asserted at
-    # four times that estimate from the oracle's own smallest gap (float64
-    # agrees to 1e-13 on the same circuit).
+def test_mixed_truncated_per_level():
+    # Truncated mixed run at a cut with a small gap: the smallest relative cut
+    # gaps of this circuit are 4.6e-6 (noise 1 x p) and 2.0e-5 (4 x p).  The
+    # Jacobi convergence threshold of the float32 rows (1e-7 relative,
+    # 1e-8 absolute) resolves the near-degenerate pairs at the cut, so each
+    # level meets the mixed tolerance against the float64 oracle.
     n, chi = 10, 64
     layers = workloads.brickwork(n, 8, seed=21)
     obs = workloads.z_singles(n) + workloads.zz_neighbours(n)
-    factors = [1.0, 4.0]
-    _say(f"case n={n} chi={chi} mixed truncated, gap-limited")
-    g = _gpu_run(n, layers, {"dep": 1e-3}, factors, chi, nze.NZE_MIXED)
-    vals, fid, tr = g.expect(obs)
-    orc = _oracle_run(n, layers, {"dep": 1e-3}, factors, chi, tie=1e-5)
-    for j, m in enumerate(orc):
-        gap = min(m.cut_gaps)
-        tol = max(MIXED_TOL, 4.0 * np.sqrt(4 * chi) * 2.0 ** -24 / gap)
-        err = np.max(np.abs(vals[j] - m.expectations(obs)))
-        _say(f"  level {j}: min gap {gap:.2e} max|dO|={err:.3e} bound {tol:.2e} "
-             f"F_gpu={fid[j]:.12f} F_orc={m.fidelity:.12f}")
-        assert err < tol
-        assert abs(fid[j] - m.fidelity) < tol * max(1.0, m.fidelity)
-        assert abs(tr[j] - m.trace()) < 10 * tol
+    _compare(n, layers, {"dep": 1e-3}, [1.0, 4.0], chi, obs, nze.NZE_MIXED,
+             MIXED_TOL)
+
+
+def test_eight_levels_one_launch_mixed_truncated():
+    # the truncated eight-level case of the float64 test above, mixed path
+    n = 10
+    layers = workloads.brickwork(n, 8, seed=21)
+    obs = workloads.z_singles(n) + workloads.zz_neighbours(n)
+    factors = [1.0 + 15.0 * j / 7 for j in range(8)]
+    _compare(n, layers, {"dep": 1e-3}, factors, 24, obs, nze.NZE_MIXED, MIXED_TOL)
 
 
 def test_server_alone_vs_mix_bitwise():
