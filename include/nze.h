@@ -229,7 +229,10 @@ int mpo_apply_layer_batch(mpo_t* const* hs, int32_t k, const int32_t* n_gates,
  *   trace    : [n_levels] float64 out, Tr(rho) of the emulated (truncated,
  *              un-renormalised) state; 1 while nothing is truncated (NULL ok).
  * Synchronises the stream.  Errors: NZE_EINVAL, NZE_EHIP, NZE_ENOCONV,
- * NZE_ENUM (earlier asynchronous failures are reported here). */
+ * NZE_ENUM (earlier asynchronous failures are reported here).  NZE_ENUM also
+ * when a level's trace c_I is zero or a value is not finite, which happens
+ * when the truncations removed the identity string (degenerate spectra of
+ * Clifford states): values, fidelity and trace are still written. */
 int mpo_expect(mpo_t* h, int32_t n_obs, const uint8_t* paulis, double* values,
                double* fidelity, double* trace);
 
@@ -283,6 +286,14 @@ int mpo_profile(mpo_t* h, double* ms_out);
  * Synchronises.  NZE_EINVAL for a bad level or bond. */
 int mpo_bond_spectrum(mpo_t* h, int32_t lv, int32_t l, double* s_out,
                       int32_t cap, int32_t* count);
+
+/* MPO entanglement entropy at bond (l, l+1) of level lv (App. A.1):
+ * S_l = -sum_i p_i ln p_i with p_i = s_i^2 / sum_j s_j^2, over the Schmidt
+ * values s_i that mpo_bond_spectrum reports (natural logarithm; 0 for a
+ * product across the bond, ln k for k equal values).  The spectrum launch
+ * moves the orthogonality centre as mpo_bond_spectrum does.  Synchronises.
+ * Errors as mpo_bond_spectrum; NZE_ENUM for a zero or non-finite spectrum. */
+int mpo_bond_entropy(mpo_t* h, int32_t lv, int32_t l, double* entropy);
 
 /* Waits for the handle's queued work and reports deferred errors
  * (NZE_ENOCONV, NZE_ENUM, NZE_EHIP). */
@@ -408,6 +419,13 @@ int nze_kernel_rowortho(int32_t precision, int32_t R, int32_t C, void* X,
                         void* stream);
 
 /* ------------------------------------------------------------------ misc */
+/* Releases the library's internal device and pinned host buffers (launch
+ * metadata staging, kernel-hook scratch) after waiting for the device.  For
+ * an orderly process exit before the HIP runtime tears down; later calls
+ * allocate them again.  Handles stay valid.  Not thread-safe against
+ * concurrent calls of the library. */
+void nze_shutdown(void);
+
 const char* nze_strerror(int code);
 const char* nze_last_error(void);
 const char* nze_version(void);

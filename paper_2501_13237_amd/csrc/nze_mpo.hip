@@ -760,7 +760,11 @@ int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& 
   const void* fn = prec == NZE_FP64 ? reinterpret_cast<const void*>(&k_layer_f64)
                    : x2 ? reinterpret_cast<const void*>(&k_layer_f32x2)
                         : reinterpret_cast<const void*>(&k_layer_f32);
-  HIPCHK(hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(NT), args, 0, stream));
+  const hipError_t le = hipLaunchCooperativeKernel(fn, dim3((unsigned)grid), dim3(NT), args, 0, stream);
+  if (le != hipSuccess) {
+    restore();
+    return hip_fail(le, "hipLaunchCooperativeKernel (layer)");
+  }
   return NZE_OK;
 }
 
@@ -831,10 +835,17 @@ extern "C" int mpo_expect(mpo_t* h, int32_t n_obs, const uint8_t* paulis,
     HIPCHK(hipMemcpyAsync(&lI[l], lg + (size_t)(l * 2) * (n + 1) + n, 8, hipMemcpyDeviceToHost, h->stream));
   }
   HIPCHK(hipStreamSynchronize(h->stream));
+  bool finite = true;
   for (int l = 0; l < L; ++l) {
     if (fidelity) fidelity[l] = scal[(size_t)l * SC_COUNT + SC_FID];
     if (trace) trace[l] = cI[l] * std::exp(lI[l] + scal[(size_t)l * SC_COUNT + SC_LOG]);
+    // <P> = c_P / c_I is undefined when the truncations removed the identity
+    // string (c_I = 0); the outputs are still written
+    if (!(cI[l] != 0.0) || !std::isfinite(cI[l])) finite = false;
+    for (int o = 0; o < n_obs; ++o)
+      if (!std::isfinite(values[(size_t)l * n_obs + o])) finite = false;
   }
+  if (!finite) return fail(NZE_ENUM, "readout not finite: the trace c_I of a level is zero or not finite");
   return NZE_OK;
 }
 
@@ -919,6 +930,26 @@ extern "C" int mpo_bond_spectrum(mpo_t* h, int32_t lv, int32_t l, double* s_out,
   return NZE_OK;
 }
 
+extern "C" int mpo_bond_entropy(mpo_t* h, int32_t lv, int32_t l, double* entropy) {
+  if (!h || !entropy) return fail(NZE_EINVAL, "bad arguments");
+  std::vector<double> sv((size_t)4 * h->cfg.chi_max);
+  int32_t count = 0;
+  int rc = mpo_bond_spectrum(h, lv, l, sv.data(), (int32_t)sv.size(), &count);
+  if (rc) return rc;
+  const int k = std::min<int>(count, (int)sv.size());
+  // S_l = -sum_i p_i ln p_i with p_i = s_i^2 / sum_j s_j^2 (natural log)
+  double tot = 0.0;
+  for (int i = 0; i < k; ++i) tot += sv[i] * sv[i];
+  if (!(tot > 0.0) || !std::isfinite(tot)) return fail(NZE_ENUM, "bond spectrum is zero or not finite");
+  double e = 0.0;
+  for (int i = 0; i < k; ++i) {
+    const double p = sv[i] * sv[i] / tot;
+    if (p > 0.0) e -= p * std::log(p);
+  }
+  *entropy = e;
+  return NZE_OK;
+}
+
 // ------------------------------------------------------ kernel-level hooks
 
 namespace nze {
@@ -967,6 +998,31 @@ int hook_scratch(char** out) {
 }
 
 }  // namespace
+
+extern "C" void nze_shutdown(void) {
+  {
+    std::lock_guard<std::mutex> a(g_stage_mu), b(g_hook_mu);
+    if (g_stage.empty() && !g_hook.dev) return;   // nothing was allocated
+  }
+  // wait for every queued use of these buffers first
+  (void)hipDeviceSynchronize();
+  {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    for (auto& kv : g_stage) {
+      Staging* st = kv.second;
+      for (int b = 0; b < 2; ++b) {
+        if (st->copied[b]) (void)hipEventDestroy(st->copied[b]);
+        if (st->host[b]) (void)hipHostFree(st->host[b]);
+      }
+      if (st->dev) (void)hipFree(st->dev);
+      delete st;
+    }
+    g_stage.clear();
+  }
+  std::lock_guard<std::mutex> lk(g_hook_mu);
+  if (g_hook.dev) (void)hipFree(g_hook.dev);
+  g_hook.dev = nullptr;
+}
 
 extern "C" int nze_kernel_theta(int32_t precision, int32_t cl, int32_t cm,
                                 int32_t cr, const void* A, const void* B,

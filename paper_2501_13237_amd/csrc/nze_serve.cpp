@@ -99,6 +99,10 @@ extern "C" void nze_server_free(nze_server_t* s) {
   delete s;
 }
 
+namespace {
+constexpr int MAX_LAUNCH_MPOS = 256;   // resident workgroups of the double kernel
+}  // namespace
+
 extern "C" int nze_server_submit(nze_server_t* s, const nze_job_spec* spec,
                                  int64_t* job_id) {
   if (!s || !spec || !job_id) return fail(NZE_EINVAL, "bad submit arguments");
@@ -110,6 +114,8 @@ extern "C" int nze_server_submit(nze_server_t* s, const nze_job_spec* spec,
   const size_t need = mpo_footprint(&cfg);
   if (need == 0) return fail(NZE_EINVAL, "invalid job configuration");
   if (need > s->arena_bytes) return fail(NZE_ENOMEM, "job larger than the arena");
+  if (spec->n_levels > MAX_LAUNCH_MPOS)
+    return fail(NZE_EINVAL, "job has more levels than one layer launch holds (256)");
   if (spec->n_layers < 0 || (spec->n_layers > 0 && (!spec->layer_gates || !spec->ptm)))
     return fail(NZE_EINVAL, "bad layers");
   if (spec->n_obs < 0 || (spec->n_obs > 0 && !spec->paulis))
@@ -128,6 +134,17 @@ extern "C" int nze_server_submit(nze_server_t* s, const nze_job_spec* spec,
     p_tot += (size_t)L * g * 256;
   }
   if (ls_tot > 0 && !spec->left_sites) { delete j; return fail(NZE_EINVAL, "no left sites"); }
+  // the layers are checked here, so that a bad job is refused at submission
+  // instead of failing the shared launches of the jobs resident beside it
+  for (int t = 0; t < spec->n_layers; ++t) {
+    const int32_t* ls = spec->left_sites + j->layer_off[t];
+    for (int i = 0; i < j->layer_gates[t]; ++i) {
+      if (ls[i] < 0 || ls[i] + 1 >= spec->n || (i > 0 && ls[i] - ls[i - 1] < 2)) {
+        delete j;
+        return fail(NZE_EINVAL, "layer sites outside the chain, unsorted or overlapping");
+      }
+    }
+  }
   j->left_sites.assign(spec->left_sites, spec->left_sites + ls_tot);
   j->ptm.assign(spec->ptm, spec->ptm + p_tot);
   j->n_obs = spec->n_obs;
@@ -141,14 +158,6 @@ extern "C" int nze_server_submit(nze_server_t* s, const nze_job_spec* spec,
 }
 
 namespace {
-
-constexpr int MAX_LAUNCH_MPOS = 256;   // resident workgroups of the double kernel
-
-int levels_of(nze_server* s, mpo_t* h) {
-  for (Job* j : s->active)
-    if (j->h == h) return j->cfg.n_levels;
-  return 1;
-}
 
 int finish(nze_server* s, Job* j) {
   const int L = j->cfg.n_levels;
@@ -193,43 +202,67 @@ extern "C" int nze_server_step(nze_server_t* s, int32_t* n_active,
     s->queue.pop_front();
     s->active.push_back(j);
   }
-  // one layer of every resident job, batched per precision
-  for (int prec = 0; prec < 2; ++prec) {
-    std::vector<mpo_t*> hs;
-    std::vector<int32_t> ng;
-    std::vector<const int32_t*> ls;
-    std::vector<const double*> pt;
-    for (Job* j : s->active) {
-      if (j->cfg.precision != prec || j->layer >= (int)j->layer_gates.size()) continue;
-      hs.push_back(j->h);
-      ng.push_back(j->layer_gates[j->layer]);
-      ls.push_back(j->left_sites.data() + j->layer_off[j->layer]);
-      pt.push_back(j->ptm.data() + j->ptm_off[j->layer]);
+  // one layer of every resident job, batched per precision.  A job's layer
+  // counter advances once its launch is enqueued; a failing launch of several
+  // jobs is retried job by job, and a job whose own launch fails is ended
+  // with that error (its memory released) while the others go on.
+  auto launch = [&](Job* const* js, size_t k) {
+    std::vector<mpo_t*> hs(k);
+    std::vector<int32_t> ng(k);
+    std::vector<const int32_t*> ls(k);
+    std::vector<const double*> pt(k);
+    for (size_t i = 0; i < k; ++i) {
+      Job* j = js[i];
+      hs[i] = j->h;
+      ng[i] = j->layer_gates[j->layer];
+      ls[i] = j->left_sites.data() + j->layer_off[j->layer];
+      pt[i] = j->ptm.data() + j->ptm_off[j->layer];
     }
+    const int rc = mpo_apply_layer_batch(hs.data(), (int32_t)k, ng.data(), ls.data(), pt.data());
+    if (rc == NZE_OK) {
+      s->launches++;
+      for (size_t i = 0; i < k; ++i) js[i]->layer++;
+    }
+    return rc;
+  };
+  auto end_job = [&](Job* j, int rc) {
+    mpo_free(j->h);
+    j->h = nullptr;
+    s->release(j->off);
+    j->t_done = s->now();
+    j->state = rc;
+  };
+  for (int prec = 0; prec < 2; ++prec) {
+    std::vector<Job*> js;
+    for (Job* j : s->active)
+      if (j->state == 1 && j->cfg.precision == prec && j->layer < (int)j->layer_gates.size())
+        js.push_back(j);
     // launches of at most MAX_LAUNCH_MPOS MPOs (levels) each, so that every
     // launch fits the co-resident grid of the persistent kernel
     size_t b = 0;
-    while (b < hs.size()) {
+    while (b < js.size()) {
       size_t e = b;
       int mpos = 0;
-      while (e < hs.size()) {
-        const int lv = hs[e] ? levels_of(s, hs[e]) : 0;
+      while (e < js.size()) {
+        const int lv = js[e]->cfg.n_levels;
         if (e > b && mpos + lv > MAX_LAUNCH_MPOS) break;
         mpos += lv;
         ++e;
       }
-      int rc = mpo_apply_layer_batch(hs.data() + b, (int32_t)(e - b), ng.data() + b,
-                                     ls.data() + b, pt.data() + b);
-      if (rc != NZE_OK) return rc;
-      s->launches++;
+      const int rc0 = launch(js.data() + b, e - b);
+      if (rc0 != NZE_OK) {
+        for (size_t i = b; i < e; ++i) {
+          const int rc = e - b > 1 ? launch(js.data() + i, 1) : rc0;
+          if (rc != NZE_OK) end_job(js[i], rc);
+        }
+      }
       b = e;
     }
   }
-  for (Job* j : s->active)
-    if (j->layer < (int)j->layer_gates.size()) j->layer++;
   // jobs that have run all their layers: read out and release their memory
   std::vector<Job*> keep;
   for (Job* j : s->active) {
+    if (j->state != 1) continue;                 // ended by a failed launch
     if (j->layer >= (int)j->layer_gates.size()) finish(s, j);
     else keep.push_back(j);
   }

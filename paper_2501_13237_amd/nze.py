@@ -3,6 +3,7 @@
 Argument marshalling only: every step of the emulation runs in the library.
 PyTorch provides the device workspace and the stream; nothing else.
 """
+import atexit
 import ctypes
 import os
 
@@ -117,6 +118,8 @@ def lib():
     L.mpo_bond_spectrum.argtypes = [ctypes.c_void_p, ctypes.c_int32,
                                     ctypes.c_int32, c_double_p, ctypes.c_int32,
                                     c_int32_p]
+    L.mpo_bond_entropy.argtypes = [ctypes.c_void_p, ctypes.c_int32,
+                                   ctypes.c_int32, c_double_p]
     L.mpo_sync.argtypes = [ctypes.c_void_p]
     L.mpo_profile.argtypes = [ctypes.c_void_p, c_double_p]
     L.nze_kernel_theta.argtypes = [ctypes.c_int32] * 4 + [
@@ -148,6 +151,8 @@ def lib():
                                   c_double_p, c_uint8_p, c_int32_p]
     L.nze_fidelity_extrapolate.argtypes = [ctypes.c_int32, c_double_p,
                                            c_double_p, c_double_p, c_int32_p]
+    L.nze_shutdown.argtypes = []
+    L.nze_shutdown.restype = None
     for fn in ("nze_strerror",):
         getattr(L, fn).argtypes = [ctypes.c_int]
         getattr(L, fn).restype = ctypes.c_char_p
@@ -155,6 +160,9 @@ def lib():
         getattr(L, fn).argtypes = []
         getattr(L, fn).restype = ctypes.c_char_p
     _lib = L
+    # release the library's staging buffers and events before the HIP
+    # runtime is torn down at exit (atexit handlers run first)
+    atexit.register(L.nze_shutdown)
     return L
 
 
@@ -441,15 +449,20 @@ class MPO:
         _check(lib().mpo_apply_layer(self.h, ls.size,
                                      ls.ctypes.data_as(c_int32_p), _dp(p)))
 
-    def expect(self, observables):
+    def expect(self, observables, allow_nonfinite=False):
+        """(values [L][n_obs], fidelity [L], trace [L]).  A level whose
+        identity string was truncated away (trace 0) makes mpo_expect return
+        NZE_ENUM; with allow_nonfinite the outputs are returned anyway."""
         obs = np.ascontiguousarray(np.asarray(observables, dtype=np.uint8)
                                    .reshape(-1, self.n))
         vals = np.zeros((self.levels, obs.shape[0]))
         fid = np.zeros(self.levels)
         tr = np.zeros(self.levels)
-        _check(lib().mpo_expect(self.h, obs.shape[0],
-                                obs.ctypes.data_as(c_uint8_p), _dp(vals),
-                                _dp(fid), _dp(tr)))
+        rc = lib().mpo_expect(self.h, obs.shape[0],
+                              obs.ctypes.data_as(c_uint8_p), _dp(vals),
+                              _dp(fid), _dp(tr))
+        if not (allow_nonfinite and rc == NZE_ENUM):
+            _check(rc)
         return vals, fid, tr
 
     def stats(self):
@@ -474,11 +487,11 @@ class MPO:
         return out[:min(cnt.value, cap)].copy()
 
     def entanglement_entropy(self, level, bond):
-        """MPO entanglement entropy -sum p ln p, p = s^2 / sum s^2 (App. A.1)."""
-        s = self.bond_spectrum(level, bond)
-        p = s * s / np.sum(s * s)
-        p = p[p > 0]
-        return float(-np.sum(p * np.log(p)))
+        """MPO entanglement entropy at bond (bond, bond + 1) of one level
+        (mpo_bond_entropy)."""
+        e = ctypes.c_double()
+        _check(lib().mpo_bond_entropy(self.h, level, bond, ctypes.byref(e)))
+        return e.value
 
     PROFILE_NAMES = ["theta", "gram", "check", "eigh", "rot_x", "rot_w",
                      "jacobi_wait", "norms", "select", "absorb", "move_prep",

@@ -159,3 +159,44 @@ def test_ptm_compose_is_second_after_first():
     A = ptm.ptm_unitary(workloads.haar_su4(rng))
     B = ptm.ptm_gate_pauli(ptm.CX_LEFT, ptm.cat_probs("CX", 0.01))
     assert np.max(np.abs(nze.ptm_compose(A, B) - B @ A)) < 1e-14
+
+
+def _job_spec(n, chi, L, layers, n_obs=1):
+    gates = np.array([len(x) for x in layers], dtype=np.int32)
+    ls = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.int32) for x in layers]))
+    pt = np.zeros(int(gates.sum()) * L * 256)
+    for i in range(0, pt.size, 256):
+        pt[i:i + 256] = np.eye(16).reshape(-1)
+    obs = np.zeros((n_obs, n), dtype=np.uint8)
+    obs[:, 0] = 3
+    keep = (gates, ls, pt, obs)
+    spec = nze.NzeJobSpec(n, chi, L, nze.NZE_FP64, len(layers),
+                          gates.ctypes.data_as(nze.c_int32_p),
+                          ls.ctypes.data_as(nze.c_int32_p), nze._dp(pt), n_obs,
+                          obs.ctypes.data_as(nze.c_uint8_p))
+    return spec, keep
+
+
+def test_server_refuses_bad_jobs_at_submission():
+    # creation and submission touch no device: the arena pointer is only
+    # recorded.  Jobs that could never run are refused at submission, so they
+    # cannot fail the shared launches of the jobs resident beside them.
+    L = nze.lib()
+    srv = ctypes.c_void_p()
+    assert L.nze_server_create(ctypes.byref(srv), ctypes.c_void_p(1 << 20),
+                               ctypes.c_size_t(1 << 40), 8, None) == nze.NZE_OK
+    jid = ctypes.c_int64()
+    try:
+        good, k1 = _job_spec(6, 8, 2, [[0, 2, 4], [1, 3]])
+        assert L.nze_server_submit(srv, ctypes.byref(good), ctypes.byref(jid)) == nze.NZE_OK
+        too_many_levels, k2 = _job_spec(6, 8, 300, [[0, 2, 4]])
+        assert L.nze_server_submit(srv, ctypes.byref(too_many_levels),
+                                   ctypes.byref(jid)) == nze.NZE_EINVAL
+        for bad_layer in ([0, 1], [4, 2], [5], [-1, 2]):
+            bad, k3 = _job_spec(6, 8, 2, [[0, 2, 4], bad_layer])
+            assert L.nze_server_submit(srv, ctypes.byref(bad), ctypes.byref(jid)) == nze.NZE_EINVAL
+        st = ctypes.c_int32()
+        assert L.nze_server_poll(srv, 1, ctypes.byref(st), None, None, None) == nze.NZE_OK
+        assert st.value == 0                        # the good job is queued
+    finally:
+        L.nze_server_free(srv)
