@@ -295,6 +295,20 @@ int mpo_bond_spectrum(mpo_t* h, int32_t lv, int32_t l, double* s_out,
  * Errors as mpo_bond_spectrum; NZE_ENUM for a zero or non-finite spectrum. */
 int mpo_bond_entropy(mpo_t* h, int32_t lv, int32_t l, double* entropy);
 
+/* True fidelity of eq. true_fidelity (Sec. 2.1.2) between two emulated
+ * states: F = |<<a|b>>|^2 / (||a||^2 ||b||^2) for level la of handle a and
+ * level lb of handle b (same n; any chi caps and precisions), e.g. a
+ * truncated run against a run at a bond dimension that is exact (App. A.2
+ * compares F with the emulation fidelity).  The overlaps are contracted site
+ * by site in float64.  *overlap (NULL ok) receives the signed normalised
+ * overlap <<a|b>> / (||a|| ||b||).  Synchronises both handles' streams and
+ * uses the two-site scratch blocks of the handle with the larger chi cap, so
+ * neither handle may have work queued on another stream meanwhile.
+ * Errors: NZE_EINVAL, NZE_EHIP, NZE_ENUM (zero norm); deferred errors of
+ * either handle. */
+int mpo_overlap(mpo_t* a, int32_t la, mpo_t* b, int32_t lb, double* fidelity,
+                double* overlap);
+
 /* Waits for the handle's queued work and reports deferred errors
  * (NZE_ENOCONV, NZE_ENUM, NZE_EHIP). */
 int mpo_sync(mpo_t* h);

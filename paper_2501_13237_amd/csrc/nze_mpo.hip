@@ -930,6 +930,128 @@ extern "C" int mpo_bond_spectrum(mpo_t* h, int32_t lv, int32_t l, double* s_out,
   return NZE_OK;
 }
 
+// ---------------------------------------------------- MPO overlaps
+
+namespace nze {
+
+// C (M x N, float64, row-major, ldc) = op(A) B with float64 accumulation:
+// op(A)[m][k] = A[m * lda + k] (trans_a == 0) or A[k * lda + m]; B[k * ldb + n].
+// 16 x 16 output tiles, K staged through LDS in chunks of 16.
+template <typename TA, typename TB>
+__global__ __launch_bounds__(256) void k_gemm_acc64(const TA* A, int lda, int trans_a,
+                                                    const TB* B, int ldb, double* C,
+                                                    int ldc, int M, int N, int K) {
+  __shared__ double As[16][17];
+  __shared__ double Bs[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int m = blockIdx.y * 16 + ty, n = blockIdx.x * 16 + tx;
+  double acc = 0.0;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const int ka = k0 + tx, kb = k0 + ty;
+    const int am = blockIdx.y * 16 + ty;
+    double av = 0.0;
+    if (am < M && ka < K)
+      av = double(trans_a ? A[(size_t)ka * lda + am] : A[(size_t)am * lda + ka]);
+    As[ty][tx] = av;
+    Bs[ty][tx] = (kb < K && n < N) ? double(B[(size_t)kb * ldb + n]) : 0.0;
+    __syncthreads();
+    for (int kk = 0; kk < 16; ++kk) acc = fma(As[ty][kk], Bs[kk][tx], acc);
+    __syncthreads();
+  }
+  if (m < M && n < N) C[(size_t)m * ldc + n] = acc;
+}
+
+template <typename TA, typename TB>
+void overlap_site(const TA* A, int ca_l, int ca_r, const TB* B, int cb_l, int cb_r,
+                  const double* E, double* Y, double* E2, hipStream_t st) {
+  // Y (ca_l x 4 cb_r) = E (ca_l x cb_l) B (cb_l x 4 cb_r)
+  dim3 g1((4 * cb_r + 15) / 16, (ca_l + 15) / 16);
+  hipLaunchKernelGGL((k_gemm_acc64<double, TB>), g1, dim3(256), 0, st, E, cb_l, 0, B,
+                     4 * cb_r, Y, 4 * cb_r, ca_l, 4 * cb_r, cb_l);
+  // E2 (ca_r x cb_r) = A^T Y with A as (4 ca_l) x ca_r and Y as (4 ca_l) x cb_r
+  dim3 g2((cb_r + 15) / 16, (ca_r + 15) / 16);
+  hipLaunchKernelGGL((k_gemm_acc64<TA, double>), g2, dim3(256), 0, st, A, ca_r, 1, Y,
+                     cb_r, E2, cb_r, ca_r, cb_r, 4 * ca_l);
+}
+
+}  // namespace nze
+
+namespace {
+
+// <<a_la | b_lb>> of the stored (normalised-site) MPOs, contracted site by
+// site with float64 environments in the scratch buffers E0, E1 (>= chi_a
+// chi_b doubles each) and Y (>= 4 chi_a chi_b doubles).
+int overlap_raw(mpo_t* a, int la, mpo_t* b, int lb, double* E0, double* E1, double* Y,
+                hipStream_t st, double* out) {
+  const int n = a->cfg.n;
+  std::vector<int> da(n + 1), db(n + 1);
+  HIPCHK(hipMemcpyAsync(da.data(), a->slots[la].dims, 4 * (n + 1), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(db.data(), b->slots[lb].dims, 4 * (n + 1), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const double one = 1.0;
+  HIPCHK(hipMemcpyAsync(E0, &one, 8, hipMemcpyHostToDevice, st));
+  const bool fa = a->cfg.precision == NZE_FP64, fb = b->cfg.precision == NZE_FP64;
+  const size_t esa = fa ? 8 : 4, esb = fb ? 8 : 4;
+  for (int k = 0; k < n; ++k) {
+    const char* A = reinterpret_cast<const char*>(a->slots[la].sites) + (size_t)k * a->site_cap * esa;
+    const char* B = reinterpret_cast<const char*>(b->slots[lb].sites) + (size_t)k * b->site_cap * esb;
+    if (fa && fb)
+      overlap_site(reinterpret_cast<const double*>(A), da[k], da[k + 1], reinterpret_cast<const double*>(B), db[k], db[k + 1], E0, Y, E1, st);
+    else if (fa)
+      overlap_site(reinterpret_cast<const double*>(A), da[k], da[k + 1], reinterpret_cast<const float*>(B), db[k], db[k + 1], E0, Y, E1, st);
+    else if (fb)
+      overlap_site(reinterpret_cast<const float*>(A), da[k], da[k + 1], reinterpret_cast<const double*>(B), db[k], db[k + 1], E0, Y, E1, st);
+    else
+      overlap_site(reinterpret_cast<const float*>(A), da[k], da[k + 1], reinterpret_cast<const float*>(B), db[k], db[k + 1], E0, Y, E1, st);
+    HIPCHK(hipGetLastError());
+    std::swap(E0, E1);
+  }
+  HIPCHK(hipMemcpyAsync(out, E0, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return NZE_OK;
+}
+
+}  // namespace
+
+extern "C" int mpo_overlap(mpo_t* a, int32_t la, mpo_t* b, int32_t lb,
+                           double* fidelity, double* overlap) {
+  if (!a || !b || !fidelity) return fail(NZE_EINVAL, "bad arguments");
+  if (a->cfg.n != b->cfg.n) return fail(NZE_EINVAL, "MPOs of different lengths");
+  if (la < 0 || la >= a->cfg.n_levels || lb < 0 || lb >= b->cfg.n_levels)
+    return fail(NZE_EINVAL, "bad level");
+  int rc = read_errors(a);
+  if (rc) return rc;
+  if (b != a) {
+    rc = read_errors(b);
+    if (rc) return rc;
+  }
+  // scratch: the two-site and accumulator blocks of the handle with the larger
+  // chi cap, idle between layer launches (both streams were synchronised)
+  mpo_t* s = b->cfg.chi_max >= a->cfg.chi_max ? b : a;
+  const size_t es = s->cfg.precision == NZE_FP64 ? 8 : 4;
+  const size_t ca = a->cfg.chi_max, cb = b->cfg.chi_max;
+  const size_t cmax = std::max(ca, cb);
+  const size_t blk = (size_t)s->m_cap * s->m_cap * es;          // bytes of X (= of W)
+  // E0 and E1 (cmax^2 doubles each) in X, Y (4 cmax^2 doubles) in W:
+  // 16 cmax^2 es >= 16 cmax^2 * 4 bytes >= what both need
+  if (2 * cmax * cmax * 8 > blk || 4 * cmax * cmax * 8 > blk)
+    return fail(NZE_EINVAL, "overlap scratch too small");
+  double* E0 = reinterpret_cast<double*>(s->slots[0].X);
+  double* E1 = E0 + cmax * cmax;
+  double* Y = reinterpret_cast<double*>(s->slots[0].W);
+  const hipStream_t st = s->stream;
+  double ab = 0.0, aa = 0.0, bb = 0.0;
+  rc = overlap_raw(a, la, b, lb, E0, E1, Y, st, &ab);
+  if (!rc) rc = overlap_raw(a, la, a, la, E0, E1, Y, st, &aa);
+  if (!rc) rc = overlap_raw(b, lb, b, lb, E0, E1, Y, st, &bb);
+  if (rc) return rc;
+  if (!(aa > 0.0) || !(bb > 0.0) || !std::isfinite(ab)) return fail(NZE_ENUM, "zero or non-finite norm");
+  const double c = ab / std::sqrt(aa * bb);
+  *fidelity = c * c;
+  if (overlap) *overlap = c;
+  return NZE_OK;
+}
+
 extern "C" int mpo_bond_entropy(mpo_t* h, int32_t lv, int32_t l, double* entropy) {
   if (!h || !entropy) return fail(NZE_EINVAL, "bad arguments");
   std::vector<double> sv((size_t)4 * h->cfg.chi_max);

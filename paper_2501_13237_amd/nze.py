@@ -120,6 +120,8 @@ def lib():
                                     c_int32_p]
     L.mpo_bond_entropy.argtypes = [ctypes.c_void_p, ctypes.c_int32,
                                    ctypes.c_int32, c_double_p]
+    L.mpo_overlap.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                              ctypes.c_int32, c_double_p, c_double_p]
     L.mpo_sync.argtypes = [ctypes.c_void_p]
     L.mpo_profile.argtypes = [ctypes.c_void_p, c_double_p]
     L.nze_kernel_theta.argtypes = [ctypes.c_int32] * 4 + [
@@ -492,6 +494,14 @@ class MPO:
         e = ctypes.c_double()
         _check(lib().mpo_bond_entropy(self.h, level, bond, ctypes.byref(e)))
         return e.value
+
+    def true_fidelity(self, level, other, other_level):
+        """F = |<<a|b>>|^2 / (||a||^2 ||b||^2) against level other_level of
+        the MPO handle ``other`` (mpo_overlap)."""
+        f, c = ctypes.c_double(), ctypes.c_double()
+        _check(lib().mpo_overlap(self.h, level, other.h, other_level,
+                                 ctypes.byref(f), ctypes.byref(c)))
+        return f.value
 
     PROFILE_NAMES = ["theta", "gram", "check", "eigh", "rot_x", "rot_w",
                      "jacobi_wait", "norms", "select", "absorb", "move_prep",

@@ -1,0 +1,131 @@
+"""The steps after the emulation, fed with GPU results: fidelity
+extrapolation over bond dimensions with criterion 1 (Sec. 2.2.2 (A),
+App. B.1), the weighted log-linear noise fit with its fallbacks
+(Sec. 2.2.2 (B), App. B.2), and the true fidelity against the emulation
+fidelity (eq. true_fidelity, App. A.2).  Each is compared with the same step
+of the oracle pipeline on the same seeded inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fits
+from oracle import mpo as ompo
+from oracle import ptm
+from paper_2501_13237_amd import nze, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle(n, layers, noise, c, chi):
+    nz = ptm.Noise(**noise).scaled(c)
+    m = ompo.PauliMPO(n, chi)
+    for ls, us in layers:
+        m.apply_layer(ls, [ptm.ptm_noisy_gate(U, nz) for U in us])
+    return m
+
+
+def test_fidelity_extrapolation_over_chi_on_gpu_runs():
+    # one noise level at chi 8, 16, 24, 32 (n = 10, depth 10): <Z_i> against
+    # the emulation fidelity, extrapolated to F = 1 by the library, against the
+    # oracle's runs and extrapolation
+    n, noise, c = 10, {"dep": 2e-3}, 1.0
+    layers = workloads.brickwork(n, 10, seed=51)
+    obs = workloads.z_singles(n)
+    chis = [8, 16, 24, 32]
+    gv, gf, ov, of = [], [], [], []
+    for chi in chis:
+        m = nze.MPO(n, chi, 1, nze.NZE_FP64)
+        nze.run_circuit(m, layers, noise, [c])
+        v, f, _ = m.expect(obs)
+        m.close()
+        o = _oracle(n, layers, noise, c, chi)
+        gv.append(v[0]); gf.append(f[0])
+        ov.append(o.expectations(obs)); of.append(o.fidelity)
+    gv, ov = np.array(gv), np.array(ov)
+    _say(f"fidelities gpu {np.array(gf)} oracle {np.array(of)}")
+    assert np.max(np.abs(gv - ov)) < 1e-10
+    assert np.max(np.abs(np.array(gf) - np.array(of))) < 1e-10
+    assert gf[0] < gf[-1] < 1.0
+    exact = _oracle(n, layers, noise, c, 1024).expectations(obs)   # exact at n = 10
+    n_conv = 0
+    for i in range(n):
+        vg, conv_g = nze.fidelity_extrapolate(gv[:, i], gf)
+        vo = fits.fidelity_extrapolation(ov[:, i], of)
+        conv_o = fits.converged(ov[:, i], of)
+        assert abs(vg - vo) < 1e-8
+        assert conv_g == conv_o
+        n_conv += conv_g
+        _say(f"  Z_{i}: extrapolated {vg:+.6f} (chi 32 {gv[-1, i]:+.6f}, exact {exact[i]:+.6f}) "
+             f"converged={conv_g}")
+    _say(f"  {n_conv}/{n} observables pass criterion 1")
+
+
+def test_loglin_noise_fit_and_fallback_on_gpu_levels():
+    # the n = 8 workload's four levels {1, 2, 4, 8} x 1e-3 from the GPU: the
+    # weighted log-linear fit to lambda* = 1e-3 over the amplified levels
+    # (criteria 2-3, App. B.2 weights), and the fallback to the three-
+    # parameter exponential when criterion 2 leaves fewer than two points
+    w = workloads.plain_fp64_n8(seed=0)
+    layers = w.circuit()
+    m = nze.MPO(w.n, w.chi, len(w.factors), nze.NZE_FP64)
+    nze.run_circuit(m, layers, w.noise, w.factors)
+    vals, fid, _ = m.expect(w.observables)
+    m.close()
+    orc = [_oracle(w.n, layers, w.noise, c, w.chi) for c in w.factors]
+    oval = np.array([o.expectations(w.observables) for o in orc])
+    ofid = np.array([o.fidelity for o in orc])
+    lam = np.array(w.factors) * w.noise["dep"]
+    target = w.noise["dep"]
+    methods = set()
+    for i in range(len(w.observables)):
+        v, coef, used, mu = nze.extrapolate(lam[1:], vals[1:, i], fid[1:], target,
+                                            nze.NZE_LOGLIN_W)
+        vo, mo, co, uo = fits.nzne(lam[1:], oval[1:, i], ofid[1:], target)
+        assert {nze.NZE_LOGLIN_W: "loglin", nze.NZE_EXP3: "exp3"}[mu] == mo
+        assert abs(v - vo) < 1e-9 and np.array_equal(used, uo)
+        methods.add(mo)
+        # criterion 2 with threshold 1 excludes every point: the direct
+        # exponential fit on all four levels takes over
+        v2, _, used2, mu2 = nze.extrapolate(lam, vals[:, i], fid, target,
+                                            nze.NZE_LOGLIN_W, small=1.0)
+        vo2, mo2, _, _ = fits.nzne(lam, oval[:, i], ofid, target, small=1.0)
+        assert mu2 == nze.NZE_EXP3 and mo2 == "exp3"
+        assert abs(v2 - vo2) < 1e-7 * max(1.0, abs(vo2))
+    _say(f"methods used: {sorted(methods)}")
+
+
+def test_true_fidelity_against_emulation_fidelity():
+    # n = 8: truncated runs (chi 4, 8, 16) against the exact run (chi = 256)
+    # of the same circuit; the true fidelity F (eq. true_fidelity) from the
+    # library's MPO overlap against the oracle's full Pauli vectors, and the
+    # emulation fidelity beside it (App. A.2 reports emulation <= true)
+    n, noise = 8, {"dep": 5e-3}
+    layers = workloads.brickwork(n, 8, seed=61)
+    factors = [1.0, 3.0]
+    exact = nze.MPO(n, 256, len(factors), nze.NZE_FP64)
+    nze.run_circuit(exact, layers, noise, factors)
+    for chi in (4, 8, 16):
+        for prec, tol in ((nze.NZE_FP64, 1e-10), (nze.NZE_MIXED, 1e-5)):
+            m = nze.MPO(n, chi, len(factors), prec)
+            nze.run_circuit(m, layers, noise, factors)
+            st, _ = m.stats()
+            for j, c in enumerate(factors):
+                F = m.true_fidelity(j, exact, j)
+                o = _oracle(n, layers, noise, c, chi)
+                ref = _oracle(n, layers, noise, c, 256)
+                a, b = o.pauli_vector(), ref.pauli_vector()
+                Fo = (a @ b) ** 2 / ((a @ a) * (b @ b))
+                _say(f"chi={chi} prec={prec} level {j}: true F gpu {F:.10f} oracle {Fo:.10f}, "
+                     f"emulation F {st[j]['fidelity']:.10f} (oracle {o.fidelity:.10f})")
+                assert abs(F - Fo) < tol
+                assert abs(st[j]["fidelity"] - o.fidelity) < tol
+            # the exact run against itself
+            assert abs(exact.true_fidelity(0, exact, 0) - 1.0) < 1e-12
+            m.close()
+    exact.close()
