@@ -167,8 +167,13 @@ typedef struct mpo_config {
   double jacobi_abs;   /* absolute part of that threshold;
                           0 -> 1e-15 (FP64) / 1e-8 (mixed)                    */
   int32_t max_sweeps;  /* Jacobi sweep cap (<= 40); 0 -> 40                   */
-  int32_t block;       /* Jacobi row-block width b (pairs are 2b rows);
-                          0 -> chosen by the built-in tuner                   */
+  int32_t block;       /* Jacobi row-block width b (pairs are 2b rows); the
+                          kernels are built for b = 16.  16: the default
+                          launch rules and schedule; 0: b = 16 with the
+                          group size, kernel build and schedule of the tuning
+                          record for (precision, chi_max, n_levels) when
+                          nze_tune (or nze_tuning_set) made one, else the
+                          defaults.  Other values: NZE_EINVAL                */
 } mpo_config;
 
 /* Device bytes the workspace of mpo_init must hold for cfg (0 if cfg is
@@ -431,6 +436,47 @@ int nze_kernel_rowortho(int32_t precision, int32_t R, int32_t C, void* X,
                         void* W, double tol_rel, double tol_abs,
                         int32_t max_sweeps, double* norms, int32_t* sweeps,
                         void* stream);
+
+/* ------------------------------------------------------------------ tuner */
+/* Launch and schedule parameters of the layer kernel for one batch shape
+ * (precision, chi cap, MPOs per launch).  None changes the arithmetic of a
+ * pair visit except the cross-block-only schedule, which changes the order of
+ * the Jacobi rotations (results then agree within the path's tolerance, not
+ * bitwise). */
+typedef struct nze_tuning {
+  int32_t block;             /* Jacobi row-block width b (16)                  */
+  int32_t group_scale;       /* workgroups per MPO: 1 = the pairs of one Jacobi
+                                round, 2 = twice that (rounds alternate between
+                                two workgroup sets), when the CUs allow       */
+  int32_t kernel;            /* 1 = one workgroup per CU, 2 = two per CU
+                                (float kernel with scalar rotations)          */
+  int32_t cross_sweeps;      /* early Jacobi sweeps whose pair solves take only
+                                the cross-block rotations ...                 */
+  int32_t cross_min_blocks;  /* ... in problems of at least this many blocks  */
+  double ms_per_svd;         /* measured time per SVD of the tuning trial     */
+} nze_tuning;
+
+/* Device bytes nze_tune needs for (chi, precision, n_mpos). */
+size_t nze_tune_footprint(int32_t chi, int32_t precision, int32_t n_mpos);
+
+/* Measures the layer kernel on n_mpos synthetic saturated blocks of size
+ * 4 chi x 4 chi (standard normal entries with row scales over four decades,
+ * all blocks in one launch) for every candidate group size, kernel build and
+ * cross-block schedule, twice each, and keeps the fastest (a candidate must
+ * beat the previous best by 2 %).  The record is cached in the process for
+ * (chi, precision, n_mpos) and written to *best.  MPOs created afterwards
+ * with mpo_config.block = 0 and that shape take it (group size and kernel
+ * build per launch; the schedule at mpo_init).  workspace: device memory of
+ * nze_tune_footprint bytes, 256-byte aligned, caller-owned; stream as in
+ * mpo_init.  Synchronises.  Errors: NZE_EINVAL, NZE_ENOMEM, NZE_EHIP,
+ * NZE_ENOCONV. */
+int nze_tune(int32_t chi, int32_t precision, int32_t n_mpos, void* workspace,
+             size_t ws_bytes, void* stream, nze_tuning* best);
+
+/* Reads (NZE_EINVAL when absent) or installs a cached tuning record, e.g.
+ * one saved from an earlier process.  nze_tuning_set checks the fields. */
+int nze_tuning_get(int32_t chi, int32_t precision, int32_t n_mpos, nze_tuning* out);
+int nze_tuning_set(int32_t chi, int32_t precision, int32_t n_mpos, const nze_tuning* t);
 
 /* ------------------------------------------------------------------ misc */
 /* Releases the library's internal device and pinned host buffers (launch

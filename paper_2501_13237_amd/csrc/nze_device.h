@@ -18,7 +18,7 @@ constexpr int CHI_LIMIT = 512;   // largest chi_max (select sorts 4*chi keys)
 constexpr int SMEM_DOUBLES = 6400;
 
 enum { OP_NONE = 0, OP_GATE_LR = 1, OP_GATE_RL = 2, OP_MOVE_LR = 3,
-       OP_MOVE_RL = 4 };
+       OP_MOVE_RL = 4, OP_JACOBI = 5 };   // OP_JACOBI: SVD of X alone (tuning)
 
 // per-MPO float64 scalars
 enum { SC_LOG = 0, SC_FID = 1, SC_MAXDISC = 2, SC_MINGAP = 3, SC_F2 = 4,
@@ -47,6 +47,9 @@ struct Slot {
   double tau, tie, tol_rel, tol_abs;
   int max_sweeps, pad;
   double* prof;     // [PROF_N] constant-rate clock ticks per phase (WG 0)
+  // Jacobi schedule: the first cross_sweeps sweeps of problems with at least
+  // cross_min_blocks row blocks take cross-block inner steps only
+  int cross_sweeps, cross_min_blocks;
 };
 
 // phase timers of workgroup 0 of each MPO
@@ -68,8 +71,9 @@ struct PhaseClock {
 
 struct Step {
   int op;    // OP_*
-  int k;     // gate: left site; move: site the centre leaves
-  int ptm;   // gate: index of its 16x16 PTM in the launch's PTM array
+  int k;     // gate: left site; move: site the centre leaves; jacobi: rows
+  int ptm;   // gate: index of its 16x16 PTM in the launch's PTM array;
+             // jacobi: columns
   int pad;
 };
 

@@ -94,6 +94,9 @@ __device__ __forceinline__ void layer_body(const Slot* slots,
       case OP_MOVE_RL:
         ok = op_move<T, VEC>(s, op.k, op.op == OP_MOVE_LR, g, G, grp, smem);
         break;
+      case OP_JACOBI:
+        ok = op_jacobi<T, VEC>(s, op.k, op.ptm, g, G, grp, smem);
+        break;
       default:
         break;
     }
@@ -375,7 +378,41 @@ struct mpo_handle {
   int centre;
   std::vector<Slot> slots;        // host copies, one per level
   int64_t layers;
+  bool tuned;                     // cfg.block == 0: launches follow the tuner
 };
+
+namespace {
+
+// Tuner records, keyed by (precision, chi cap, MPOs per launch).  The group
+// size and the kernel build never change a result (every pair visit computes
+// the same numbers whichever workgroup runs it); the cross-block-only
+// schedule changes the rotations, so it is fixed per handle at mpo_init.
+struct TuneKey {
+  int prec, chi, nmpo;
+  bool operator<(const TuneKey& o) const {
+    if (prec != o.prec) return prec < o.prec;
+    if (chi != o.chi) return chi < o.chi;
+    return nmpo < o.nmpo;
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, nze_tuning> g_tune;
+
+bool tune_lookup(int prec, int chi, int nmpo, nze_tuning* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(TuneKey{prec, chi, nmpo});
+  if (it == g_tune.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+// Per-launch overrides of the automatic rules (0 = automatic).
+struct LaunchChoice {
+  int group_scale = 0;   // 1: pairs per round; 2: doubled groups
+  int kernel = 0;        // 1: one workgroup per CU; 2: two per CU (float)
+};
+
+}  // namespace
 
 namespace {
 
@@ -519,8 +556,11 @@ extern "C" int mpo_init(mpo_t** out, const mpo_config* cfg,
   if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
     return fail(NZE_EINVAL, "workspace must be a 256-byte aligned device pointer");
   mpo_config c = *cfg;
+  const bool tuned = c.block == 0;
   fill_defaults(c);
-  if (c.block != BW) return fail(NZE_EINVAL, "unsupported Jacobi block width");
+  if (c.block != BW) return fail(NZE_EINVAL, "unsupported Jacobi block width (16)");
+  nze_tuning tune_rec;
+  const bool have_tune = tuned && tune_lookup(c.precision, c.chi_max, c.n_levels, &tune_rec);
   const Layout lay = layout_of(&c);
   if (ws_bytes < lay.total) return fail(NZE_ENOMEM, "workspace smaller than mpo_footprint(cfg)");
   DevInfo di;
@@ -535,6 +575,7 @@ extern "C" int mpo_init(mpo_t** out, const mpo_config* cfg,
   h->m_cap = 4 * c.chi_max;
   h->centre = 0;
   h->layers = 0;
+  h->tuned = tuned;
   const size_t es = c.precision == NZE_FP64 ? 8 : 4;
   const int L = c.n_levels, n = c.n;
   for (int l = 0; l < L; ++l) {
@@ -560,6 +601,8 @@ extern "C" int mpo_init(mpo_t** out, const mpo_config* cfg,
     s.tol_abs = c.jacobi_abs;
     s.max_sweeps = c.max_sweeps;
     s.prof = reinterpret_cast<double*>(h->ws + lay.prof) + (size_t)l * PF_N;
+    s.cross_sweeps = have_tune ? tune_rec.cross_sweeps : 8;
+    s.cross_min_blocks = have_tune ? tune_rec.cross_min_blocks : 64;
     h->slots.push_back(s);
   }
   std::vector<double> init((size_t)4 * n);
@@ -601,7 +644,7 @@ extern "C" void mpo_free(mpo_t* h) {
 namespace {
 int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& plans,
                  const int32_t* n_gates, const double* const* ptm,
-                 const std::vector<int>& saved_centre);
+                 const std::vector<int>& saved_centre, const LaunchChoice* forced = nullptr);
 }  // namespace
 
 extern "C" int mpo_apply_layer_batch(mpo_t* const* hs, int32_t k,
@@ -639,7 +682,7 @@ namespace {
 // failure before the launch the handles' centres are restored.
 int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& plans,
                  const int32_t* n_gates, const double* const* ptm,
-                 const std::vector<int>& saved_centre) {
+                 const std::vector<int>& saved_centre, const LaunchChoice* forced) {
   const int prec = hs[0]->cfg.precision;
   const hipStream_t stream = hs[0]->stream;
   size_t nsteps = 0, nmpo = 0, nptm = 0;
@@ -667,9 +710,26 @@ int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& 
   }
   long long want_tot = 0;
   for (int x : gm) want_tot += x;
+  // the tuner's choice for this batch shape, when every handle follows it
+  LaunchChoice ch;
+  if (forced) {
+    ch = *forced;
+  } else {
+    bool all_tuned = true, same_chi = true;
+    for (int j = 0; j < k; ++j) {
+      all_tuned = all_tuned && hs[j]->tuned;
+      same_chi = same_chi && hs[j]->cfg.chi_max == hs[0]->cfg.chi_max;
+    }
+    nze_tuning t;
+    if (all_tuned && same_chi && tune_lookup(prec, hs[0]->cfg.chi_max, (int)nmpo, &t)) {
+      ch.group_scale = t.group_scale;
+      ch.kernel = t.kernel;
+    }
+  }
   // float batches that ask for more groups than one per CU run the kernel
   // built for two workgroups per CU (independent MPOs then share each CU)
-  const bool x2 = prec != NZE_FP64 && di.occ_f32x2 >= 2 && want_tot > (long long)di.occ[1] * di.cus;
+  bool x2 = prec != NZE_FP64 && di.occ_f32x2 >= 2 && want_tot > (long long)di.occ[1] * di.cus;
+  if (prec != NZE_FP64 && di.occ_f32x2 >= 2 && ch.kernel) x2 = ch.kernel == 2;
   const int occ = prec == NZE_FP64 ? di.occ[0] : (x2 ? di.occ_f32x2 : di.occ[1]);
   const int resident = std::max(1, occ * di.cus);
   if ((int)nmpo > resident) {
@@ -692,7 +752,10 @@ int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& 
   // between two sets of workgroups, and the accumulator rotation of one round
   // runs beside the next round's data visits.  Two such workgroups sharing a
   // CU gain nothing (measured), hence only on idle CUs.
-  if (!x2 && want_tot * 2 <= (long long)di.cus && occ == 1) {
+  const bool can_double = want_tot * 2 <= (long long)resident;
+  const bool dbl = ch.group_scale ? (ch.group_scale == 2 && can_double)
+                                  : (!x2 && want_tot * 2 <= (long long)di.cus && occ == 1);
+  if (dbl) {
     for (int& x : gm) x *= 2;
     want_tot *= 2;
   }
@@ -927,6 +990,150 @@ extern "C" int mpo_bond_spectrum(mpo_t* h, int32_t lv, int32_t l, double* s_out,
   HIPCHK(hipMemcpyAsync(s_out, s.sval, (size_t)m * 8, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   *count = r;
+  return NZE_OK;
+}
+
+// ------------------------------------------------------------- tuner
+
+namespace nze {
+
+__device__ inline uint64_t mix64(uint64_t z) {
+  // splitmix64 finaliser (Steele, Lea, Flood 2014)
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Synthetic two-site blocks for the tuner: X[i][j] = d_i z_ij with standard
+// normal z (Box-Muller on counter-based uniforms) and row scales d_i falling
+// over four decades, a spectrum graded like that of a saturated update.
+template <typename T>
+__global__ void k_fill_graded(const Slot* slots, int R, int C, uint64_t seed) {
+  const Slot s = slots[blockIdx.y];
+  T* X = reinterpret_cast<T*>(s.X);
+  const size_t total = (size_t)R * C;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const uint64_t h1 = mix64(seed ^ (2 * e + 1) ^ ((uint64_t)blockIdx.y << 44));
+    const uint64_t h2 = mix64(h1 ^ 0xD1B54A32D192ED03ull);
+    const double u1 = ((double)(h1 >> 11) + 0.5) * 0x1p-53;
+    const double u2 = (double)(h2 >> 11) * 0x1p-53;
+    const double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    const int i = (int)(e / C);
+    X[e] = T(z * exp(-9.210340371976184 * i / R));   // 10^(-4 i / R)
+  }
+}
+
+}  // namespace nze
+
+extern "C" size_t nze_tune_footprint(int32_t chi, int32_t precision, int32_t n_mpos) {
+  mpo_config c{};
+  c.n = 2;
+  c.chi_max = chi;
+  c.n_levels = n_mpos;
+  c.precision = precision;
+  return mpo_footprint(&c);
+}
+
+extern "C" int nze_tune(int32_t chi, int32_t precision, int32_t n_mpos, void* workspace,
+                        size_t ws_bytes, void* stream, nze_tuning* best) {
+  if (!best || chi < 4 || chi > CHI_LIMIT || n_mpos < 1 ||
+      (precision != NZE_FP64 && precision != NZE_MIXED))
+    return fail(NZE_EINVAL, "bad tuning arguments");
+  mpo_config c{};
+  c.n = 2;
+  c.chi_max = chi;
+  c.n_levels = n_mpos;
+  c.precision = precision;
+  c.block = BW;
+  mpo_t* h = nullptr;
+  int rc = mpo_init(&h, &c, nullptr, workspace, ws_bytes, stream);
+  if (rc) return rc;
+  DevInfo di;
+  rc = dev_info(di);
+  if (rc) { mpo_free(h); return rc; }
+  const int m = 4 * chi, nb = (m + BW - 1) / BW;
+  std::vector<int> kernels{1};
+  if (precision == NZE_MIXED && di.occ_f32x2 >= 2) kernels.push_back(2);
+  std::vector<std::pair<int, int>> cross{{0, 64}};
+  if (nb >= 16) { cross.push_back({4, nb}); cross.push_back({8, nb}); }
+  if (nb >= 64) cross.push_back({8, 64});
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  std::vector<std::vector<Step>> plans{{Step{OP_JACOBI, m, m, 0}}};
+  const int32_t ng = 0;
+  const double* no_ptm = nullptr;
+  std::vector<int> centre{h->centre};
+  const hipStream_t st = h->stream;
+  nze_tuning top{};
+  top.ms_per_svd = 1e300;
+  for (int kern : kernels)
+    for (int scale = 1; scale <= 2; ++scale)
+      for (const auto& cr : cross) {
+        for (Slot& sl : h->slots) { sl.cross_sweeps = cr.first; sl.cross_min_blocks = cr.second; }
+        LaunchChoice ch;
+        ch.group_scale = scale;
+        ch.kernel = kern;
+        float best_ms = 1e30f;
+        for (int rep = 0; rep < 2 && !rc; ++rep) {
+          // the slots live in the launch metadata; a separate staging copy
+          // feeds the fill kernel
+          char* dslots = nullptr;
+          rc = stage(st, h->slots.data(), sizeof(Slot) * h->slots.size(), &dslots);
+          if (rc) break;
+          const Slot* ds = reinterpret_cast<const Slot*>(dslots);
+          if (precision == NZE_FP64)
+            hipLaunchKernelGGL(k_fill_graded<double>, dim3(256, n_mpos), dim3(256), 0, st, ds, m, m, 12345ull);
+          else
+            hipLaunchKernelGGL(k_fill_graded<float>, dim3(256, n_mpos), dim3(256), 0, st, ds, m, m, 12345ull);
+          if (hipGetLastError() != hipSuccess) { rc = fail(NZE_EHIP, "tuner fill launch"); break; }
+          if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(NZE_EHIP, "event"); break; }
+          rc = launch_plans(&h, 1, plans, &ng, &no_ptm, centre, &ch);
+          if (rc) break;
+          if (hipEventRecord(e1, st) != hipSuccess) { rc = fail(NZE_EHIP, "event"); break; }
+          rc = read_errors(h);
+          if (rc) break;
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = fail(NZE_EHIP, "event"); break; }
+          best_ms = std::min(best_ms, ms);
+        }
+        if (rc) break;
+        const double per = best_ms / n_mpos;
+        // a candidate must be 2 % faster than the one before it to replace it
+        if (per < 0.98 * top.ms_per_svd) {
+          top.block = BW;
+          top.group_scale = scale;
+          top.kernel = kern;
+          top.cross_sweeps = cr.first;
+          top.cross_min_blocks = cr.second;
+          top.ms_per_svd = per;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  mpo_free(h);
+  if (rc) return rc;
+  *best = top;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[TuneKey{precision, chi, n_mpos}] = top;
+  return NZE_OK;
+}
+
+extern "C" int nze_tuning_get(int32_t chi, int32_t precision, int32_t n_mpos, nze_tuning* out) {
+  if (!out) return fail(NZE_EINVAL, "NULL output");
+  if (!tune_lookup(precision, chi, n_mpos, out)) return fail(NZE_EINVAL, "no tuning record for this shape");
+  return NZE_OK;
+}
+
+extern "C" int nze_tuning_set(int32_t chi, int32_t precision, int32_t n_mpos, const nze_tuning* t) {
+  if (!t || t->block != BW || (t->group_scale != 1 && t->group_scale != 2) ||
+      (t->kernel != 1 && t->kernel != 2) || t->cross_sweeps < 0 || t->cross_sweeps > MAXSW ||
+      t->cross_min_blocks < 1)
+    return fail(NZE_EINVAL, "bad tuning record");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[TuneKey{precision, chi, n_mpos}] = *t;
   return NZE_OK;
 }
 
@@ -1195,20 +1402,16 @@ extern "C" int nze_kernel_theta(int32_t precision, int32_t cl, int32_t cm,
   return NZE_OK;
 }
 
-extern "C" int nze_kernel_rowortho(int32_t precision, int32_t R, int32_t C,
-                                   void* X, void* W, double tol_rel,
-                                   double tol_abs, int32_t max_sweeps,
-                                   double* norms, int32_t* sweeps,
-                                   void* stream) {
-  if (precision != NZE_FP64 && precision != NZE_MIXED) return fail(NZE_EINVAL, "precision");
-  if (R < 1 || R > 4 * CHI_LIMIT || C < 4 || (C & 3) || !X || !W || !norms || max_sweeps < 1 || max_sweeps > MAXSW)
-    return fail(NZE_EINVAL, "bad rowortho arguments");
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+namespace {
+
+// The block one-sided Jacobi of the layer kernel on caller buffers, with its
+// counters, barrier words, norms and row order in the 64 KiB scratch `scr`
+// (device memory; its first 8 KiB are cleared by a fill kernel here).
+int rowortho_impl(int32_t precision, int32_t R, int32_t C, void* X, void* W,
+                  double tol_rel, double tol_abs, int32_t max_sweeps, double* norms,
+                  int32_t* sweeps, hipStream_t st, char* scr) {
   DevInfo di;
   int rc = dev_info(di);
-  if (rc) return rc;
-  char* scr;
-  rc = hook_scratch(&scr);
   if (rc) return rc;
   double* dscal = reinterpret_cast<double*>(scr);
   int* dctr = reinterpret_cast<int*>(scr + 256);
@@ -1217,7 +1420,8 @@ extern "C" int nze_kernel_rowortho(int32_t precision, int32_t R, int32_t C,
   int* dperm = reinterpret_cast<int*>(scr + 8192 + 8 * 4 * CHI_LIMIT);   // R ints (row order)
   static_assert(8192 + 12 * 4 * CHI_LIMIT <= HOOK_BYTES, "hook scratch too small");
   static_assert(256 + 4 * CT_COUNT <= 2048, "hook counters overlap the barrier");
-  HIPCHK(hipMemsetAsync(scr, 0, 8192, st));
+  hipLaunchKernelGGL(k_fill_int, dim3(8), dim3(256), 0, st, reinterpret_cast<int*>(scr), 8192 / 4, 0);
+  HIPCHK(hipGetLastError());
   Slot s;
   std::memset(&s, 0, sizeof(s));
   s.scal = dscal;
@@ -1229,6 +1433,8 @@ extern "C" int nze_kernel_rowortho(int32_t precision, int32_t R, int32_t C,
   s.tol_rel = tol_rel;
   s.tol_abs = tol_abs;
   s.max_sweeps = max_sweeps;
+  s.cross_sweeps = 8;
+  s.cross_min_blocks = 64;
   const int occ = di.occ[precision == NZE_FP64 ? 0 : 1];
   const int G = std::max(1, std::min((R + 31) / 32, occ * di.cus));
   int a_R = R, a_C = C, a_G = G;
@@ -1248,3 +1454,30 @@ extern "C" int nze_kernel_rowortho(int32_t precision, int32_t R, int32_t C,
   if (ctr[CT_ERR] & ERR_NOCONV) return fail(NZE_ENOCONV, "rowortho hit the sweep cap");
   return NZE_OK;
 }
+
+int rowortho_args(int32_t precision, int32_t R, int32_t C, const void* X, const void* W,
+                  const double* norms, int32_t max_sweeps) {
+  if (precision != NZE_FP64 && precision != NZE_MIXED) return fail(NZE_EINVAL, "precision");
+  if (R < 1 || R > 4 * CHI_LIMIT || C < 4 || (C & 3) || !X || !W || !norms || max_sweeps < 1 || max_sweeps > MAXSW)
+    return fail(NZE_EINVAL, "bad rowortho arguments (1 <= R <= 2048, C a positive multiple of 4, sweeps 1..40)");
+  return NZE_OK;
+}
+
+}  // namespace
+
+extern "C" int nze_kernel_rowortho(int32_t precision, int32_t R, int32_t C,
+                                   void* X, void* W, double tol_rel,
+                                   double tol_abs, int32_t max_sweeps,
+                                   double* norms, int32_t* sweeps,
+                                   void* stream) {
+  int rc = rowortho_args(precision, R, C, X, W, norms, max_sweeps);
+  if (rc) return rc;
+  char* scr;
+  rc = hook_scratch(&scr);
+  if (rc) return rc;
+  return rowortho_impl(precision, R, C, X, W, tol_rel, tol_abs, max_sweeps, norms, sweeps,
+                       reinterpret_cast<hipStream_t>(stream), scr);
+}
+
+
+

@@ -614,14 +614,15 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
     sclk.lap(s.prof, PF_SWEEP);
     const double F2 = __hip_atomic_load(&s.scal[SC_F2], __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
-    // early sweeps of a large problem (64 blocks or more), while every pair
-    // still rotated in the sweep before: the inner solves take only their 256
+    // early sweeps of a large problem (cross_min_blocks blocks or more; 64
+    // by default, the first cross_sweeps = 8 sweeps), while every pair still
+    // rotated in the sweep before: the inner solves take only their 256
     // cross-block rotations.  Far from convergence the outer sweeps, not the
     // pair solves, set the pace, and the rows are re-blocked by norm at every
     // sweep, so pairs left inside a block meet as cross pairs later; every
     // later sweep runs full inner sweeps, which polish all pairs.
     bool cross_only = false;
-    if (nb >= 64 && sw < 8)
+    if (nb >= s.cross_min_blocks && sw < s.cross_sweeps)
       cross_only = sw == 0 ||
                    __hip_atomic_load(&s.ctr[CT_ROT + sw - 1], __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT) == rounds * npair;
@@ -785,6 +786,20 @@ __device__ __forceinline__ bool op_gate(const Slot& s, int k, bool ltr, const do
   const bool ok = group_sync(grp);
   clk.lap(s.prof, PF_ABSORB);
   return ok;
+}
+
+// SVD of the R x C block already in X alone (the tuner's unit of work):
+// W = I, the Jacobi, then the squared row norms.
+template <typename T, int VEC = 1>
+__device__ __forceinline__ bool op_jacobi(const Slot& s, int R, int C, int g, int G,
+                                          Group& grp, double* smem) {
+  T* X = reinterpret_cast<T*>(s.X);
+  T* W = reinterpret_cast<T*>(s.W);
+  set_identity(W, R, g, G);
+  if (!group_sync(grp)) return false;
+  if (!phase_jacobi<T, VEC>(s, X, W, R, C, g, G, grp, smem)) return false;
+  phase_norms<T>(s, X, R, C, g, G);
+  return group_sync(grp);
 }
 
 // Centre move away from site c: to c+1 (ltr) or c-1.

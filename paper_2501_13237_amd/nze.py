@@ -53,6 +53,13 @@ class NzeFitOpts(ctypes.Structure):
                 ("ref_sign", ctypes.c_int32), ("b_max", ctypes.c_double)]
 
 
+class NzeTuning(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("group_scale", ctypes.c_int32),
+                ("kernel", ctypes.c_int32), ("cross_sweeps", ctypes.c_int32),
+                ("cross_min_blocks", ctypes.c_int32),
+                ("ms_per_svd", ctypes.c_double)]
+
+
 class NzeJobSpec(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("chi_max", ctypes.c_int32),
                 ("n_levels", ctypes.c_int32), ("precision", ctypes.c_int32),
@@ -153,6 +160,12 @@ def lib():
                                   c_double_p, c_uint8_p, c_int32_p]
     L.nze_fidelity_extrapolate.argtypes = [ctypes.c_int32, c_double_p,
                                            c_double_p, c_double_p, c_int32_p]
+    L.nze_tune_footprint.argtypes = [ctypes.c_int32] * 3
+    L.nze_tune_footprint.restype = ctypes.c_size_t
+    L.nze_tune.argtypes = [ctypes.c_int32] * 3 + [ctypes.c_void_p, ctypes.c_size_t,
+                                                  ctypes.c_void_p, ctypes.POINTER(NzeTuning)]
+    L.nze_tuning_get.argtypes = [ctypes.c_int32] * 3 + [ctypes.POINTER(NzeTuning)]
+    L.nze_tuning_set.argtypes = [ctypes.c_int32] * 3 + [ctypes.POINTER(NzeTuning)]
     L.nze_shutdown.argtypes = []
     L.nze_shutdown.restype = None
     for fn in ("nze_strerror",):
@@ -384,20 +397,56 @@ def kernel_theta(A, B, ptm16, ltr=True):
     return X
 
 
-def kernel_rowortho(X, tol_rel, tol_abs, max_sweeps=40):
+def kernel_rowortho(X, tol_rel, tol_abs, max_sweeps=40, W=None):
     """Block one-sided Jacobi on the rows of the device matrix X (in place);
     returns (W, squared row norms, sweeps)."""
     import torch
     prec = NZE_FP64 if X.dtype == torch.float64 else NZE_MIXED
     R, C = X.shape
-    W = torch.empty((R, R), dtype=X.dtype, device=X.device)
+    if W is None:
+        W = torch.empty((R, R), dtype=X.dtype, device=X.device)
     norms = np.zeros(R)
     sw = ctypes.c_int32()
-    _check(lib().nze_kernel_rowortho(prec, R, C, X.data_ptr(), W.data_ptr(),
-                                     tol_rel, tol_abs, max_sweeps, _dp(norms),
-                                     ctypes.byref(sw),
-                                     torch.cuda.current_stream().cuda_stream))
+    fn = lib().nze_kernel_rowortho
+    _check(fn(prec, R, C, X.data_ptr(), W.data_ptr(), tol_rel, tol_abs, max_sweeps,
+              _dp(norms), ctypes.byref(sw), torch.cuda.current_stream().cuda_stream))
     return W, norms, sw.value
+
+
+# ------------------------------------------------------------------ tuner
+
+_TUNING_FIELDS = [f for f, _ in NzeTuning._fields_]
+
+
+def tune(chi, precision, n_mpos, stream=None):
+    """nze_tune: measures the candidate launch parameters for this batch
+    shape on synthetic saturated blocks and caches the fastest; returns it."""
+    import torch
+    nbytes = int(lib().nze_tune_footprint(chi, precision, n_mpos))
+    if nbytes == 0:
+        raise NzeError(NZE_EINVAL, "invalid tuning shape")
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    ptr = (ws.data_ptr() + 255) & ~255
+    st = stream if stream is not None else torch.cuda.current_stream()
+    t = NzeTuning()
+    _check(lib().nze_tune(chi, precision, n_mpos, ctypes.c_void_p(ptr),
+                          ctypes.c_size_t(nbytes), ctypes.c_void_p(st.cuda_stream),
+                          ctypes.byref(t)))
+    del ws
+    return {f: getattr(t, f) for f in _TUNING_FIELDS}
+
+
+def tuning_get(chi, precision, n_mpos):
+    """The cached tuning record for this shape, or None."""
+    t = NzeTuning()
+    if lib().nze_tuning_get(chi, precision, n_mpos, ctypes.byref(t)) != NZE_OK:
+        return None
+    return {f: getattr(t, f) for f in _TUNING_FIELDS}
+
+
+def tuning_set(chi, precision, n_mpos, record):
+    t = NzeTuning(*[record[f] for f in _TUNING_FIELDS])
+    _check(lib().nze_tuning_set(chi, precision, n_mpos, ctypes.byref(t)))
 
 
 # ------------------------------------------------------------------- MPOs

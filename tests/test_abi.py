@@ -200,3 +200,16 @@ def test_server_refuses_bad_jobs_at_submission():
         assert st.value == 0                        # the good job is queued
     finally:
         L.nze_server_free(srv)
+
+
+def test_tuning_records_are_checked_and_cached():
+    # host-only: no device work is done by get / set
+    assert nze.tuning_get(96, nze.NZE_MIXED, 3) is None
+    rec = dict(block=16, group_scale=2, kernel=1, cross_sweeps=4, cross_min_blocks=24,
+               ms_per_svd=1.5)
+    nze.tuning_set(96, nze.NZE_MIXED, 3, rec)
+    assert nze.tuning_get(96, nze.NZE_MIXED, 3) == rec
+    for bad in (dict(rec, block=32), dict(rec, group_scale=3), dict(rec, kernel=0),
+                dict(rec, cross_sweeps=-1)):
+        with pytest.raises(nze.NzeError):
+            nze.tuning_set(96, nze.NZE_MIXED, 3, bad)

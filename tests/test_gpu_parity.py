@@ -582,3 +582,21 @@ def test_plain_n8_extrapolation_both_readings():
     _say(f"n=8 quadratic NZNE (levels 2,4,8 -> p): max err vs dense {max(err_a):.2e}; "
          f"ZNE (levels 1,2,4,8 -> 0): max err vs dense {max(err_b):.2e}")
     assert max(err_a) < 1e-4 and max(err_b) < 1e-3
+
+
+@pytest.mark.parametrize("precision", [nze.NZE_FP64, nze.NZE_MIXED])
+def test_rowortho_sweep_cap_reports_noconv(precision):
+    # three sweeps cannot orthogonalise a graded 1024 x 1024 block; the last
+    # sweep the cap allows always measures the largest off-diagonal (no
+    # forced cross-block-only sweep there), so the cap is an error, not a
+    # benign hit at the rounding floor
+    R = C = 1024
+    rng = np.random.default_rng(5)
+    Xin = rng.standard_normal((R, C)) * np.logspace(0, -4, R)[:, None]
+    _say(f"rowortho cap R={R} prec={precision}")
+    X = _torch_dev(Xin, precision)
+    fp64 = precision == nze.NZE_FP64
+    with pytest.raises(nze.NzeError) as e:
+        nze.kernel_rowortho(X, 1e-13 if fp64 else 1e-7, 1e-15 if fp64 else 1e-8,
+                            max_sweeps=3)
+    assert e.value.code == nze.NZE_ENOCONV
