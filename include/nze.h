@@ -478,6 +478,23 @@ int nze_tune(int32_t chi, int32_t precision, int32_t n_mpos, void* workspace,
 int nze_tuning_get(int32_t chi, int32_t precision, int32_t n_mpos, nze_tuning* out);
 int nze_tuning_set(int32_t chi, int32_t precision, int32_t n_mpos, const nze_tuning* t);
 
+/* nze_kernel_rowortho for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernel and results, but the Jacobi's
+ * counters, barrier words, row norms and row order live in a static 64 KiB
+ * array in each GPU's memory (held until the process ends) instead of the
+ * scratch the library allocates on first use.  The call allocates nothing:
+ * no hipMalloc, no pinned host memory; the host-side norms copy goes to the
+ * caller's array.  The limit is the hook's: 1 <= R <= 2048 (NZE_EINVAL
+ * beyond).  Every call on one GPU shares that GPU's array, whose first 8 KiB
+ * are cleared by a fill kernel at the start of each call: calls that overlap
+ * on one GPU (other streams or host threads) race and must be serialised by
+ * the caller. */
+int nze_kernel_rowortho_static(int32_t precision, int32_t R, int32_t C, void* X,
+                               void* W, double tol_rel, double tol_abs,
+                               int32_t max_sweeps, double* norms, int32_t* sweeps,
+                               void* stream);
+
 /* ------------------------------------------------------------------ misc */
 /* Releases the library's internal device and pinned host buffers (launch
  * metadata staging, kernel-hook scratch) after waiting for the device.  For

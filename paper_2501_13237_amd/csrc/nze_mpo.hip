@@ -1479,5 +1479,43 @@ extern "C" int nze_kernel_rowortho(int32_t precision, int32_t R, int32_t C,
                        reinterpret_cast<hipStream_t>(stream), scr);
 }
 
+namespace {
 
+// Scratch of the allocation-free variant: one 64 KiB array in every GPU's
+// memory for the life of the process.  In host code `scratch` names a host
+// stand-in; its device address comes from hipGetSymbolAddress, once per
+// device, and only that address is ever passed to a kernel or a copy.
+__device__ __align__(256) char scratch[HOOK_BYTES];
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;
+
+int static_scratch(char** out) {
+  int dev;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) { *out = it->second; return NZE_OK; }
+  char* ptr = nullptr;
+  HIPCHK(hipGetSymbolAddress(reinterpret_cast<void**>(&ptr), HIP_SYMBOL(scratch)));
+  if (!ptr) return fail(NZE_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+  g_scratch_ptr[dev] = ptr;
+  *out = ptr;
+  return NZE_OK;
+}
+
+}  // namespace
+
+extern "C" int nze_kernel_rowortho_static(int32_t precision, int32_t R, int32_t C,
+                                          void* X, void* W, double tol_rel,
+                                          double tol_abs, int32_t max_sweeps,
+                                          double* norms, int32_t* sweeps,
+                                          void* stream) {
+  int rc = rowortho_args(precision, R, C, X, W, norms, max_sweeps);
+  if (rc) return rc;
+  char* scr;
+  rc = static_scratch(&scr);
+  if (rc) return rc;
+  return rowortho_impl(precision, R, C, X, W, tol_rel, tol_abs, max_sweeps, norms, sweeps,
+                       reinterpret_cast<hipStream_t>(stream), scr);
+}
 

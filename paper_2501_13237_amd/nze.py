@@ -138,6 +138,7 @@ def lib():
         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
         ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_int32,
         c_double_p, c_int32_p, ctypes.c_void_p]
+    L.nze_kernel_rowortho_static.argtypes = L.nze_kernel_rowortho.argtypes
     L.nze_server_create.argtypes = [ctypes.POINTER(ctypes.c_void_p),
                                     ctypes.c_void_p, ctypes.c_size_t,
                                     ctypes.c_int32, ctypes.c_void_p]
@@ -397,9 +398,11 @@ def kernel_theta(A, B, ptm16, ltr=True):
     return X
 
 
-def kernel_rowortho(X, tol_rel, tol_abs, max_sweeps=40, W=None):
+def kernel_rowortho(X, tol_rel, tol_abs, max_sweeps=40, W=None, static=False):
     """Block one-sided Jacobi on the rows of the device matrix X (in place);
-    returns (W, squared row norms, sweeps)."""
+    returns (W, squared row norms, sweeps).  static: the allocation-free entry
+    point (nze_kernel_rowortho_static); W may then be passed in, so that the
+    call allocates nothing."""
     import torch
     prec = NZE_FP64 if X.dtype == torch.float64 else NZE_MIXED
     R, C = X.shape
@@ -407,7 +410,7 @@ def kernel_rowortho(X, tol_rel, tol_abs, max_sweeps=40, W=None):
         W = torch.empty((R, R), dtype=X.dtype, device=X.device)
     norms = np.zeros(R)
     sw = ctypes.c_int32()
-    fn = lib().nze_kernel_rowortho
+    fn = lib().nze_kernel_rowortho_static if static else lib().nze_kernel_rowortho
     _check(fn(prec, R, C, X.data_ptr(), W.data_ptr(), tol_rel, tol_abs, max_sweeps,
               _dp(norms), ctypes.byref(sw), torch.cuda.current_stream().cuda_stream))
     return W, norms, sw.value
