@@ -22,10 +22,13 @@ enum { OP_NONE = 0, OP_GATE_LR = 1, OP_GATE_RL = 2, OP_MOVE_LR = 3,
 
 // per-MPO float64 scalars
 enum { SC_LOG = 0, SC_FID = 1, SC_MAXDISC = 2, SC_MINGAP = 3, SC_F2 = 4,
-       SC_KEPT = 5, SC_FLOPS = 6, SC_CAPQ = 7, SC_COUNT = 8 };
+       SC_KEPT = 5, SC_FLOPS = 6, SC_CAPQ = 7, SC_TOT = 8, SC_ABOVE = 9,
+       SC_COUNT = 10 };
+// SC_TOT: ||X||^2 of the block entering the last Jacobi; SC_ABOVE: number of
+// singular values above tau s_1 at the last selection
 // per-MPO int counters
 enum { CT_RANK = 0, CT_ERR = 1, CT_MAXSW = 2, CT_UPD = 3, CT_SWTOT = 4,
-       CT_OFFMAX = 5, CT_CAPHIT = 6, CT_ROT = 8, CT_BVER = 8 + MAXSW,
+       CT_OFFMAX = 5, CT_CAPHIT = 6, CT_NSMAX = 7, CT_ROT = 8, CT_BVER = 8 + MAXSW,
        CT_WVER = CT_BVER + 136, CT_COUNT = CT_WVER + 136 };
 // CT_BVER / CT_WVER: per row block (<= 136), visits whose data rows / whose
 // accumulator rows are final
@@ -50,6 +53,9 @@ struct Slot {
   // Jacobi schedule: the first cross_sweeps sweeps of problems with at least
   // cross_min_blocks row blocks take cross-block inner steps only
   int cross_sweeps, cross_min_blocks;
+  // float64 refinement workspace of the mixed path (nullptr: no refinement):
+  // [chi * m_cap] + [chi * chi] + [chi * m_cap] doubles
+  double* R64;
 };
 
 // phase timers of workgroup 0 of each MPO

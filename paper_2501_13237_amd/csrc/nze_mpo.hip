@@ -310,8 +310,15 @@ namespace {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t sites, X, W, Rm, norms, perm, sval, dims, scal, ctr, env, envlog, prof, total;
+  size_t sites, X, W, Rm, norms, perm, sval, dims, scal, ctr, env, envlog, prof, r64, total;
 };
+
+// doubles of one slot's refinement workspace (the layout of r64_rows /
+// r64_square in the device code)
+size_t r64_doubles(size_t chi, size_t m) {
+  const size_t rows = chi + BAND, sq = std::max<size_t>(rows * rows, 1088);
+  return 2 * rows * m + sq;
+}
 
 bool cfg_valid(const mpo_config* c) {
   return c && c->n >= 2 && c->n <= 4096 && c->chi_max >= 1 &&
@@ -340,6 +347,9 @@ Layout layout_of(const mpo_config* c) {
   o.env = take(L * 2 * (n + 1) * chi * 8);
   o.envlog = take(L * 2 * (n + 1) * 8);
   o.prof = take(L * PF_N * 8);
+  // mixed path: float64 refinement workspace per level
+  // (chi + 16 rows: the kept directions and the polished band below the cut)
+  o.r64 = take(c->precision == NZE_MIXED ? L * r64_doubles(chi, m) * 8 : 0);
   o.total = off;
   return o;
 }
@@ -494,7 +504,7 @@ void fill_defaults(mpo_config& c) {
   if (c.trunc_tol <= 0) c.trunc_tol = f64 ? 1e-14 : 1e-7;
   if (c.tie_tol <= 0) c.tie_tol = f64 ? 1e-10 : 1e-5;
   if (c.jacobi_tol <= 0) c.jacobi_tol = f64 ? 1e-13 : 1e-7;
-  if (c.jacobi_abs <= 0) c.jacobi_abs = f64 ? 1e-15 : 1e-8;
+  if (c.jacobi_abs <= 0) c.jacobi_abs = f64 ? 1e-15 : 1e-9;
   if (c.max_sweeps <= 0) c.max_sweeps = MAXSW;   // dense near-degenerate spectra can need > 30
   if (c.block <= 0) c.block = BW;
 }
@@ -601,6 +611,9 @@ extern "C" int mpo_init(mpo_t** out, const mpo_config* cfg,
     s.tol_abs = c.jacobi_abs;
     s.max_sweeps = c.max_sweeps;
     s.prof = reinterpret_cast<double*>(h->ws + lay.prof) + (size_t)l * PF_N;
+    s.R64 = c.precision == NZE_MIXED
+                ? reinterpret_cast<double*>(h->ws + lay.r64) + (size_t)l * r64_doubles(c.chi_max, h->m_cap)
+                : nullptr;
     s.cross_sweeps = have_tune ? tune_rec.cross_sweeps : 8;
     s.cross_min_blocks = have_tune ? tune_rec.cross_min_blocks : 64;
     h->slots.push_back(s);

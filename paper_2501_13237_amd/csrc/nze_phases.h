@@ -123,7 +123,7 @@ __device__ void set_identity(T* W, int n, int g, int G) {
 // X <- (R x 1)(M_k M_{k+1}); also W = I and F2 = ||X||^2.
 template <typename T>
 __device__ void phase_theta(const Slot& s, int k, bool ltr, const double* R,
-                            int g, int G, double* smem) {
+                            int g, int G, double* smem, bool count = true) {
   typedef typename AccT<T>::type acc_t;
   const int cl = s.dims[k], cm = s.dims[k + 1], cr = s.dims[k + 2];
   const T* A = site_ptr<T>(s, k);          // (4 cl) x cm
@@ -176,7 +176,7 @@ __device__ void phase_theta(const Slot& s, int k, bool ltr, const double* R,
         }
     }
   }
-  if (g == 0 && tid == 0)   // contraction 2 (4cl) cm (4cr) + superoperator 512 cl cr
+  if (count && g == 0 && tid == 0)   // contraction 2 (4cl) cm (4cr) + superoperator 512 cl cr
     s.scal[SC_FLOPS] += 32.0 * cl * cm * cr + 512.0 * cl * cr;
   set_identity(reinterpret_cast<T*>(s.W), ltr ? 4 * cl : 4 * cr, g, G);
 }
@@ -605,6 +605,7 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
       for (int i = threadIdx.x; i < R; i += NT) s.perm[i] = idx[i];
       if (threadIdx.x == 0) {
         s.scal[SC_F2] = f2;
+        if (sw == 0) s.scal[SC_TOT] = f2;
         s.ctr[CT_OFFMAX] = 0;
       }
       if (sw == 0)
@@ -684,7 +685,8 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
 // One workgroup: sort the squared norms, pick the rank, update fidelity and
 // log-scale.  gate: truncation rule with chi cap and tie rule; otherwise
 // (centre move) only numerical zeros (s_i <= tau s_1) are dropped.
-__device__ void phase_select(const Slot& s, int R, bool gate, double* smem) {
+__device__ void phase_select(const Slot& s, int R, bool gate, double* smem,
+                             bool defer = false) {
   int N = 1;
   while (N < R) N <<= 1;
   double* key = smem;
@@ -725,19 +727,24 @@ __device__ void phase_select(const Slot& s, int R, bool gate, double* smem) {
   double kept = 0.0;
   for (int i = tid; i < r; i += NT) {
     kept += fmax(key[i], 0.0);
-    s.perm[i] = idx[i];
     s.sval[i] = sqrt(fmax(key[i], 0.0));
   }
+  for (int i = tid; i < R; i += NT) s.perm[i] = idx[i];   // the whole order
   kept = block_sum(kept, red);
   if (tid == 0) {
     s.ctr[CT_RANK] = r;
     s.scal[SC_KEPT] = kept;
+    s.scal[SC_ABOVE] = above;
     if (!(tot == tot) || tot > 1e300 || !(kept > 0.0)) s.ctr[CT_ERR] |= ERR_NAN;
     if (gate) {
-      const double f = kept / tot;
-      s.scal[SC_FID] *= f;
-      s.scal[SC_LOG] += 0.5 * log(kept);
-      s.scal[SC_MAXDISC] = fmax(s.scal[SC_MAXDISC], 1.0 - f);
+      // with defer the refinement books the partial fidelity of the block it
+      // builds (refine_gate)
+      if (!defer) {
+        const double f = kept / tot;
+        s.scal[SC_FID] *= f;
+        s.scal[SC_LOG] += 0.5 * log(kept);
+        s.scal[SC_MAXDISC] = fmax(s.scal[SC_MAXDISC], 1.0 - f);
+      }
       if (r < R && key[r] > 0.0) {
         const double gap = (sqrt(key[r - 1]) - sqrt(key[r])) / s1;
         s.scal[SC_MINGAP] = fmin(s.scal[SC_MINGAP], gap);
@@ -747,6 +754,466 @@ __device__ void phase_select(const Slot& s, int R, bool gate, double* smem) {
     s.scal[SC_F2] = 0.0;
   }
   for (int i = tid; i < MAXSW; i += NT) s.ctr[CT_ROT + i] = 0;
+}
+
+// ------------------------------------------- float64 refinement (mixed)
+//
+// The float32 Jacobi leaves two kinds of error that matter for a truncated
+// state: its accumulator rows are orthonormal only to the float32 rounding
+// it has gathered (a few 1e-6 after a dozen sweeps), and its rotated data
+// rows carry absolute rounding of order eps ||X||.  The refinement keeps the
+// float32 decisions (rank, kept directions) and rebuilds the two factors in
+// float64: the kept orthonormal rows get one Newton-Schulz step
+// Q <- (3 I - Q Q^T) Q / 2 (quadratic: 1e-6 -> 1e-12), and the other factor is
+// the projection of the unrotated block onto them.  The product of the two
+// factors is then the orthogonal projection of the block onto the kept
+// subspace, and the partial fidelity kept / total is exactly that
+// projection's (Sec. 2.1.2, eq. for f_l).
+
+// C (M x N, float64, row-major ldc) = A op(B) over the group's workgroups on
+// 64 x 64 tiles with float64 MFMA: A is M x K (row-major lda), B is K x N
+// (row-major ldb) or, with TB_T, N x K (row-major ldb) used transposed.
+// K advances 16 at a time: lane (i, q) reads k = k0 + 4q .. 4q + 3 of its A
+// row as one vector, and MFMA step u takes k = k0 + 4q + u on both operands
+// (any assignment of the four k of a step to q is a valid 16x16x4 product).
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef nze_v4f type; };
+template <> struct Vec4<double> { typedef double type __attribute__((ext_vector_type(4))); };
+
+template <typename T>
+__device__ inline void load4_or0(const T* p, bool ok_all, int nvalid, double v[4]) {
+  if (ok_all && (reinterpret_cast<uintptr_t>(p) & (4 * sizeof(T) - 1)) == 0) {
+    const typename Vec4<T>::type x = *(__attribute__((address_space(1))) const typename Vec4<T>::type*)p;
+    v[0] = double(x[0]); v[1] = double(x[1]); v[2] = double(x[2]); v[3] = double(x[3]);
+  } else {
+    for (int u = 0; u < 4; ++u) v[u] = u < nvalid ? double(load1(p + u)) : 0.0;
+  }
+}
+
+template <typename TA, typename TB, bool TB_T>
+__device__ void gemm64(const TA* A, int lda, const TB* B, int ldb, double* C, int ldc,
+                       int M, int N, int K, int g, int G) {
+  typedef typename AccT<double>::type acc_t;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, q = lane >> 4;
+  const int tm = (M + 63) / 64, tn = (N + 63) / 64;
+  for (int tile = g; tile < tm * tn; tile += G) {
+    const int m0 = (tile / tn) * 64, n0 = (tile % tn) * 64;
+    const int row = m0 + 16 * w + i;
+    acc_t acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = acc_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      const int kb = k0 + 4 * q;                       // this lane's four k
+      const int nv = K - kb;                           // valid among them
+      double av[4];
+      load4_or0(A + (size_t)(row < M ? row : 0) * lda + kb, row < M && nv >= 4, row < M ? nv : 0, av);
+      double bv[4][4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = n0 + 16 * j + i;
+        if (TB_T) {
+          load4_or0(B + (size_t)(col < N ? col : 0) * ldb + kb, col < N && nv >= 4, col < N ? nv : 0, bv[j]);
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            bv[j][u] = (col < N && u < nv) ? double(load1(B + (size_t)(kb + u) * ldb + col)) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = mfma4(av[u], bv[j][u], acc[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = m0 + 16 * w + mrow<double>(q, r), cc = n0 + 16 * j + i;
+        if (rr < M && cc < N) C[(size_t)rr * ldc + cc] = acc[j][r];
+      }
+  }
+}
+
+// dst[i][c] = T(src[i][c] * scale), i < r, c < n
+template <typename T>
+__device__ void copy_r64(const double* src, int lds, int r, int n, T* dst, int ldd,
+                         double scale, int g, int G) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = g * 4 + w; i < r; i += 4 * G)
+    for (int c = lane; c < n; c += 64) dst[(size_t)i * ldd + c] = T(src[(size_t)i * lds + c] * scale);
+}
+
+// dst[a][i] = T(src[i][a] * scale), i < r, a < n (LDS transpose)
+template <typename T>
+__device__ void copy_t64(const double* src, int lds, int r, int n, T* dst, int ldd,
+                         double scale, int g, int G, double* smem) {
+  double* tile = smem;   // [32][33]
+  const int ta = (n + 31) / 32, ti = (r + 31) / 32;
+  for (int t = g; t < ta * ti; t += G) {
+    const int a0 = (t / ti) * 32, i0 = (t % ti) * 32;
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += NT) {
+      const int ii = e >> 5, al = e & 31;
+      tile[ii * 33 + al] = (i0 + ii < r && a0 + al < n) ? src[(size_t)(i0 + ii) * lds + a0 + al] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += NT) {
+      const int al = e >> 5, ii = e & 31;
+      if (i0 + ii < r && a0 + al < n)
+        dst[(size_t)(a0 + al) * ldd + i0 + ii] = T(tile[ii * 33 + al] * scale);
+    }
+  }
+  __syncthreads();
+}
+
+// Newton-Schulz iteration Q <- (3 I - Q Q^T) Q / 2 on the r rows of Q
+// (r x n, float64), ping-ponging between Q0 and Q1 with B (r x r) as scratch.
+// The largest |Q Q^T - I| entry e of the start, reduced over the group into
+// ctr[CT_NSMAX] (a maximum, so the order of the atomics does not matter),
+// sets the number of steps: each step takes e to about 3 e^2 / 4, so 1e-5
+// needs one step to reach 1e-10, 1e-3 two, 2e-2 three, 0.15 four and 0.5
+// five.  Returns the buffer holding the orthonormal rows, or nullptr when
+// the start is beyond 1/2 (outside the iteration's safe range) or a barrier
+// failed (*ok false).
+__device__ inline double* ns_rows(double* Q0, double* Q1, int n, int r, double* B,
+                                  const Slot& s, int g, int G, Group& grp, bool* ok) {
+  double* cur = Q0;
+  double* nxt = Q1;
+  *ok = false;
+  if (g == 0 && threadIdx.x == 0) s.ctr[CT_NSMAX] = 0;
+  if (!group_sync(grp)) return nullptr;
+  gemm64<double, double, true>(cur, n, cur, n, B, r, r, r, n, g, G);
+  if (!group_sync(grp)) return nullptr;
+  float emax = 0.f;
+  for (int e = g * NT + threadIdx.x; e < r * r; e += G * NT) {
+    const int i = e / r, j = e - i * r;
+    const double d = fabs(B[e] - (i == j ? 1.0 : 0.0));
+    emax = fmaxf(emax, (d == d) ? float(d) : 1e30f);
+  }
+  for (int o = 32; o > 0; o >>= 1) emax = fmaxf(emax, __shfl_xor(emax, o, 64));
+  if ((threadIdx.x & 63) == 0 && emax > 0.f) atomicMax(&s.ctr[CT_NSMAX], __float_as_int(emax));
+  if (!group_sync(grp)) return nullptr;
+  const float e0 = __int_as_float(__hip_atomic_load(&s.ctr[CT_NSMAX], __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT));
+  *ok = true;
+  if (!(e0 <= 0.5f)) return nullptr;
+  const int steps = e0 <= 1e-13f ? 0 : e0 <= 1e-5f ? 1 : e0 <= 1e-3f ? 2 : e0 <= 2e-2f ? 3
+                  : e0 <= 0.15f ? 4 : 5;
+  for (int st = 0; st < steps; ++st) {
+    if (st > 0) {
+      gemm64<double, double, true>(cur, n, cur, n, B, r, r, r, n, g, G);
+      if (!group_sync(grp)) { *ok = false; return nullptr; }
+    }
+    for (int e = g * NT + threadIdx.x; e < r * r; e += G * NT) {
+      const int i = e / r, j = e - i * r;
+      B[e] = (i == j ? 1.5 : 0.0) - 0.5 * B[e];
+    }
+    if (!group_sync(grp)) { *ok = false; return nullptr; }
+    gemm64<double, double, false>(B, r, cur, n, nxt, n, r, n, r, g, G);
+    if (!group_sync(grp)) { *ok = false; return nullptr; }
+    double* t = cur; cur = nxt; nxt = t;
+  }
+  return cur;
+}
+
+// squared norms of the r rows of A (r x n, float64) into s.norms, one wave
+// per row (a fixed summation order)
+__device__ inline void rows_norm64(const Slot& s, const double* A, int r, int n, int g, int G) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = g * 4 + w; i < r; i += 4 * G) {
+    double acc = 0.0;
+    for (int c = lane; c < n; c += 64) {
+      const double v = A[(size_t)i * n + c];
+      acc += v * v;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) s.norms[i] = acc;
+  }
+}
+
+constexpr int BAND = 16;   // kept and dropped directions polished at a cut
+
+// Refinement workspace of a slot: two (chi + BAND) x m_cap row buffers around
+// a square one of max((chi + BAND)^2, 32 x 32) doubles.
+__device__ inline size_t r64_rows(const Slot& s) { return (size_t)s.chi + BAND; }
+__device__ inline size_t r64_square(const Slot& s) {
+  const size_t c = r64_rows(s);
+  return c * c > 1088 ? c * c : 1088;   // the band's 32 x 32 vectors + 32 values
+}
+
+// One workgroup: the eigenvectors of the symmetric nb x nb (nb <= 32) float64
+// Gram in L.Gs by cyclic Jacobi sweeps (the pairing of the pair solves) until
+// every |g_uv| <= 1e-15 sqrt(g_uu g_vv), at most twelve sweeps; rows and
+// columns nb..31 are inert padding.  On return Vout (32 x 32, row u column a)
+// holds the eigenvector of column a in row u, columns in decreasing order of
+// their eigenvalue, and EVout[a] that eigenvalue.
+__device__ void band_eigh(const PairLds& L, int nb, double* Vout, double* EVout) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 32 * 32; e += NT) {
+    const int u = e >> 5, v = e & 31;
+    L.Qs[u * GLD + v] = (u == v) ? 1.0 : 0.0;
+    if (u >= nb || v >= nb) L.Gs[u * GLD + v] = (u == v) ? -1.0 - u : 0.0;
+  }
+  __syncthreads();
+  double* Ga = L.Gs;
+  double* Gb = L.Gp;
+  const int P = tid >> 4, P2 = tid & 15, u0 = 2 * P;
+  double* red = L.Gp + 2048;
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    // convergence on the entries of the current Gram
+    double worst = 0.0;
+    for (int e = tid; e < 1024; e += NT) {
+      const int u = e >> 5, v = e & 31;
+      if (u < v && v < nb) {
+        const double d = fabs(Ga[u * GLD + v]) / sqrt(fabs(Ga[u * GLD + u] * Ga[v * GLD + v]) + 1e-300);
+        worst = fmax(worst, d);
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o, 64));
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = worst;
+    __syncthreads();
+    worst = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    __syncthreads();
+    if (worst <= 1e-15) break;
+    for (int st = 0; st < 31; ++st) {
+      int p, q, p2, q2;
+      sweep_pair32(P, st, p, q);
+      sweep_pair32(P2, st, p2, q2);
+      const double app = Ga[p * GLD + p], aqq = Ga[q * GLD + q], apq = Ga[p * GLD + q];
+      const double bpp = Ga[p2 * GLD + p2], bqq = Ga[q2 * GLD + q2], bpq = Ga[p2 * GLD + q2];
+      const double g11 = Ga[p * GLD + p2], g12 = Ga[p * GLD + q2];
+      const double g21 = Ga[q * GLD + p2], g22 = Ga[q * GLD + q2];
+      const double qa = L.Qs[u0 * GLD + p2], qb = L.Qs[u0 * GLD + q2];
+      const double qc = L.Qs[(u0 + 1) * GLD + p2], qd = L.Qs[(u0 + 1) * GLD + q2];
+      double c, sn, c2, s2;
+      jacobi_cs(app, aqq, apq, 0.0, c, sn);
+      jacobi_cs(bpp, bqq, bpq, 0.0, c2, s2);
+      const double h11 = c * g11 - sn * g21, h12 = c * g12 - sn * g22;
+      const double h21 = sn * g11 + c * g21, h22 = sn * g12 + c * g22;
+      Gb[p * GLD + p2] = c2 * h11 - s2 * h12;
+      Gb[p * GLD + q2] = s2 * h11 + c2 * h12;
+      Gb[q * GLD + p2] = c2 * h21 - s2 * h22;
+      Gb[q * GLD + q2] = s2 * h21 + c2 * h22;
+      L.Qs[u0 * GLD + p2] = c2 * qa - s2 * qb;
+      L.Qs[u0 * GLD + q2] = s2 * qa + c2 * qb;
+      L.Qs[(u0 + 1) * GLD + p2] = c2 * qc - s2 * qd;
+      L.Qs[(u0 + 1) * GLD + q2] = s2 * qc + c2 * qd;
+      double* t = Ga; Ga = Gb; Gb = t;
+      __syncthreads();
+    }
+  }
+  // columns in decreasing eigenvalue order (selection by rank; ties by index)
+  if (tid < 32) {
+    const double ev = Ga[tid * GLD + tid];
+    int rank = 0;
+    for (int b = 0; b < 32; ++b) {
+      const double eb = Ga[b * GLD + b];
+      rank += (eb > ev || (eb == ev && b < tid)) ? 1 : 0;
+    }
+    for (int u = 0; u < 32; ++u) Vout[u * 32 + rank] = L.Qs[u * GLD + tid];
+    EVout[rank] = ev;
+  }
+  __syncthreads();
+}
+
+// rows [b0, b0 + nb) of M (ld columns n, float64) <- V^T rows: row a of the
+// band becomes sum_u V[u][a] row_u (V from band_eigh, 32 x 32).  Column
+// chunks of 64 are staged through LDS (32 x 65 doubles), so the rotation
+// needs no per-thread arrays.
+__device__ inline void band_rotate(double* M, int ld, int n, int b0, int nb, const double* V,
+                                   int g, int G, double* smem) {
+  double* tile = smem;   // [32][65]
+  for (int c0 = g * 64; c0 < n; c0 += G * 64) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 32 * 64; e += NT) {
+      const int u = e >> 6, cl = e & 63;
+      tile[u * 65 + cl] = (u < nb && c0 + cl < n) ? M[(size_t)(b0 + u) * ld + c0 + cl] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 32 * 64; e += NT) {
+      const int a = e >> 6, cl = e & 63;
+      if (a >= nb || c0 + cl >= n) continue;
+      double acc = 0.0;
+      for (int u = 0; u < nb; ++u) acc = fma(V[u * 32 + a], tile[u * 65 + cl], acc);
+      M[(size_t)(b0 + a) * ld + c0 + cl] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+// Gate update after phase_select(defer): float64 factors from the kept
+// directions, the block recomputed from the unchanged sites, and the
+// partial-fidelity bookkeeping of the refined projection.  Returns 1 when
+// done, 0 on a barrier failure, -1 when the kept accumulator rows are too far
+// from orthonormal for the iteration (the float32 factors are then used).
+template <typename T>
+__device__ __attribute__((noinline)) int refine_gate(const Slot& s, int k, bool ltr, const double* Rptm, int Rr,
+                           int Cc, int g, int G, Group& grp, double* smem) {
+  const int r = s.ctr[CT_RANK];
+  // the kept rows and the BAND dropped rows right below the cut
+  const int lo = r < BAND ? r : BAND;
+  const int hi = Rr - r < BAND ? Rr - r : BAND;
+  const int rr = r + hi;
+  double* A = s.R64;                                  // rr x max(Rr, Cc)
+  double* B = A + r64_rows(s) * s.m_cap;              // rr x rr, or the band's 32 x 32
+  double* C = B + r64_square(s);                      // rr x max(Rr, Cc)
+  const T* W = reinterpret_cast<const T*>(s.W);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = g * 4 + w; i < rr; i += 4 * G) {
+    const T* src = W + (size_t)s.perm[i] * Rr;
+    for (int c = lane; c < Rr; c += 64) A[(size_t)i * Rr + c] = double(load1(src + c));
+  }
+  bool ok;
+  double* Q = ns_rows(A, C, Rr, rr, B, s, g, G, grp, &ok);
+  if (!ok) return 0;
+  if (!Q) return -1;
+  double* Y = Q == A ? C : A;
+  // the block again (its sites are untouched until the gathers below)
+  phase_theta<T>(s, k, ltr, Rptm, g, G, smem, false);
+  if (!group_sync(grp)) return 0;
+  gemm64<double, T, false>(Q, Rr, reinterpret_cast<const T*>(s.X), Cc, Y, Cc, rr, Cc, Rr, g, G);
+  if (!group_sync(grp)) return 0;
+  // Rayleigh-Ritz in float64 on the band around the cut: the float32 Jacobi
+  // leaves near-degenerate directions on either side mixed by about
+  // tol / (2 relative gap); diagonalising the band's float64 Gram resolves
+  // that mixing, and the largest lo band directions are the kept ones
+  const int nb = lo + hi, b0 = r - lo;
+  if (hi > 0 && lo > 0) {
+    double* V = B;                                    // 32 x 32
+    if (g == 0) {
+      const PairLds L = pair_lds(smem);
+      // band Gram Y_b Y_b^T in float64, one (u, v) entry per thread group
+      for (int e = threadIdx.x; e < 32 * 32; e += NT) L.Gs[(e >> 5) * GLD + (e & 31)] = 0.0;
+      __syncthreads();
+      for (int uv = w; uv < nb * nb; uv += 4) {
+        const int u = uv / nb, v = uv - u * nb;
+        if (v < u) continue;
+        double acc = 0.0;
+        const double* yu = Y + (size_t)(b0 + u) * Cc;
+        const double* yv = Y + (size_t)(b0 + v) * Cc;
+        for (int c = lane; c < Cc; c += 64) acc = fma(yu[c], yv[c], acc);
+        acc = wave_sum(acc);
+        if (lane == 0) { L.Gs[u * GLD + v] = acc; L.Gs[v * GLD + u] = acc; }
+      }
+      __syncthreads();
+      double* EV = V + 1024;
+      band_eigh(L, nb, V, EV);
+      // the truncation rule again where float64 values decide it: when the
+      // cut is set by chi and its two sides lie in the band, the tie rule
+      // (drop the chained cluster whose neighbours agree within tie_tol)
+      // runs on the band's float64 values; float32 norms carry relative
+      // errors of eps s_1 / s_r, as large as tie_tol at the cut
+      if (threadIdx.x == 0) {
+        const int above = (int)s.scal[SC_ABOVE];
+        const int r0 = above < s.chi ? above : s.chi;
+        int rn = r;
+        if (r0 == s.chi && r0 < above && r0 > b0 && r0 < b0 + nb) {
+          int q = r0;
+          while (q > b0) {
+            const double a = sqrt(fmax(EV[q - 1 - b0], 0.0)), b = sqrt(fmax(EV[q - b0], 0.0));
+            if (a - b <= s.tie * a) --q; else break;
+          }
+          if (q > b0) rn = q;            // resolved inside the band
+          if (q == 0) rn = r0;           // the whole spectrum tied: keep chi
+        }
+        s.ctr[CT_RANK] = rn;
+      }
+    }
+    if (!group_sync(grp)) return 0;
+    band_rotate(Q, Rr, Rr, b0, nb, V, g, G, smem);
+    band_rotate(Y, Cc, Cc, b0, nb, V, g, G, smem);
+    if (!group_sync(grp)) return 0;
+  }
+  const int rk = s.ctr[CT_RANK];
+  rows_norm64(s, Y, rk, Cc, g, G);
+  if (!group_sync(grp)) return 0;
+  if (g == 0) {
+    double* red = smem;
+    double kept = 0.0;
+    for (int i = threadIdx.x; i < rk; i += NT) kept += s.norms[i];
+    kept = block_sum(kept, red);
+    if (threadIdx.x == 0) {
+      const double tot = s.scal[SC_TOT];
+      const double f = kept / tot;
+      if (!(kept > 0.0) || !(tot > 0.0) || !(f == f)) s.ctr[CT_ERR] |= ERR_NAN;
+      s.scal[SC_KEPT] = kept;
+      s.scal[SC_FID] *= f;
+      s.scal[SC_LOG] += 0.5 * log(kept);
+      s.scal[SC_MAXDISC] = fmax(s.scal[SC_MAXDISC], 1.0 - f);
+    }
+  }
+  if (!group_sync(grp)) return 0;
+  const double inv = 1.0 / sqrt(s.scal[SC_KEPT]);
+  T* Mk = site_ptr<T>(s, k);
+  T* Mk1 = site_ptr<T>(s, k + 1);
+  if (ltr) {   // M_k = Q^T (4cl x r), M_{k+1} = Q X0 / ||.|| (r x 4cr)
+    copy_t64<T>(Q, Rr, rk, Rr, Mk, rk, 1.0, g, G, smem);
+    copy_r64<T>(Y, Cc, rk, Cc, Mk1, Cc, inv, g, G);
+  } else {     // M_k = (Q X0)^T / ||.|| (4cl x r), M_{k+1} = Q (r x 4cr)
+    copy_t64<T>(Y, Cc, rk, Cc, Mk, rk, inv, g, G, smem);
+    copy_r64<T>(Q, Rr, rk, Rr, Mk1, Rr, 1.0, g, G);
+  }
+  return group_sync(grp) ? 1 : 0;
+}
+
+// Centre move after phase_select: the orthonormal factor from the kept data
+// rows divided by their norms, orthonormalised in float64, and the other
+// factor as the projection of the site onto it, absorbed into the neighbour
+// in float64.  The projection keeps the state whatever rotation the
+// iteration applies inside the kept span, so the move stays exact up to the
+// dropped numerical zeros.  Returns 1 when done, 0 on a barrier failure, -1
+// when the rows are too far from orthonormal (the float32 factors are used).
+template <typename T>
+__device__ __attribute__((noinline)) int refine_move(const Slot& s, int c, bool ltr, int Rr, int Cc, int g, int G,
+                           Group& grp, double* smem) {
+  const int r = s.ctr[CT_RANK];
+  double* A = s.R64;                                  // r x Cc
+  double* B = A + r64_rows(s) * s.m_cap;              // r x r
+  double* C = B + r64_square(s);                      // r x Cc
+  const T* X = reinterpret_cast<const T*>(s.X);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int i = g * 4 + w; i < r; i += 4 * G) {
+    const T* src = X + (size_t)s.perm[i] * Cc;
+    const double inv = 1.0 / s.sval[i];
+    for (int cc = lane; cc < Cc; cc += 64) A[(size_t)i * Cc + cc] = double(load1(src + cc)) * inv;
+  }
+  bool ok;
+  double* Q = ns_rows(A, C, Cc, r, B, s, g, G, grp, &ok);
+  if (!ok) return 0;
+  if (!Q) return -1;
+  double* P = Q == A ? C : A;                         // second factor / product
+  T* M = site_ptr<T>(s, c);
+  const int cl = s.dims[c], cr = s.dims[c + 1];
+  if (ltr) {
+    // M (4cl x cr) = Q^T R with R = Q M (r x cr) in B; R absorbed into site c+1
+    gemm64<double, T, false>(Q, Cc, M, cr, B, cr, r, cr, 4 * cl, g, G);
+    if (!group_sync(grp)) return 0;
+    copy_t64<T>(Q, Cc, r, Cc, M, r, 1.0, g, G, smem);
+    const int c2 = s.dims[c + 2];
+    T* Mn = site_ptr<T>(s, c + 1);                     // cr x 4c2
+    gemm64<double, T, false>(B, cr, Mn, 4 * c2, P, 4 * c2, r, 4 * c2, cr, g, G);
+    if (g == 0 && threadIdx.x == 0) s.scal[SC_FLOPS] += 8.0 * r * cr * c2;
+    if (!group_sync(grp)) return 0;
+    copy_r64<T>(P, 4 * c2, r, 4 * c2, Mn, 4 * c2, 1.0, g, G);
+    if (!group_sync(grp)) return 0;
+    if (g == 0 && threadIdx.x == 0) s.dims[c + 1] = r;
+  } else {
+    // M (cl x 4cr) = L Q with L = M Q^T (cl x r) in B; L absorbed into site c-1
+    gemm64<T, double, true>(M, Cc, Q, Cc, B, r, cl, r, Cc, g, G);
+    if (!group_sync(grp)) return 0;
+    copy_r64<T>(Q, Cc, r, Cc, M, Cc, 1.0, g, G);
+    const int c0 = s.dims[c - 1];
+    T* Mp = site_ptr<T>(s, c - 1);                     // 4c0 x cl
+    gemm64<T, double, false>(Mp, cl, B, r, P, r, 4 * c0, r, cl, g, G);
+    if (g == 0 && threadIdx.x == 0) s.scal[SC_FLOPS] += 8.0 * c0 * cl * r;
+    if (!group_sync(grp)) return 0;
+    copy_r64<T>(P, r, 4 * c0, r, Mp, r, 1.0, g, G);
+    if (!group_sync(grp)) return 0;
+    if (g == 0 && threadIdx.x == 0) s.dims[c] = r;
+  }
+  return group_sync(grp) ? 1 : 0;
 }
 
 // ----------------------------------------------------------- full ops
@@ -767,9 +1234,27 @@ __device__ __forceinline__ bool op_gate(const Slot& s, int k, bool ltr, const do
   phase_norms<T>(s, X, Rr, Cc, g, G);
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_NORMS);
-  if (g == 0) phase_select(s, Rr, true, smem);
+  if (g == 0) phase_select(s, Rr, true, smem, sizeof(T) == 4 && s.R64 != nullptr);
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_SELECT);
+  if constexpr (sizeof(T) == 4) if (s.R64 != nullptr) {
+    const int st = refine_gate<T>(s, k, ltr, R, Rr, Cc, g, G, grp, smem);
+    if (st == 0) return false;
+    if (st == 1) {
+      if (g == 0 && threadIdx.x == 0) s.dims[k + 1] = s.ctr[CT_RANK];
+      const bool ok = group_sync(grp);
+      clk.lap(s.prof, PF_ABSORB);
+      return ok;
+    }
+    // no refinement: the partial fidelity of the float32 factors
+    if (g == 0 && threadIdx.x == 0) {
+      const double kept = s.scal[SC_KEPT], f = kept / s.scal[SC_TOT];
+      s.scal[SC_FID] *= f;
+      s.scal[SC_LOG] += 0.5 * log(kept);
+      s.scal[SC_MAXDISC] = fmax(s.scal[SC_MAXDISC], 1.0 - f);
+    }
+    if (!group_sync(grp)) return false;
+  }
   const int r = s.ctr[CT_RANK];
   const double inv = 1.0 / sqrt(s.scal[SC_KEPT]);
   T* Mk = site_ptr<T>(s, k);
@@ -855,6 +1340,14 @@ __device__ __forceinline__ bool op_move(const Slot& s, int c, bool ltr, int g, i
   if (g == 0) phase_select(s, Rr, false, smem);
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_SELECT);
+  if constexpr (sizeof(T) == 4) if (s.R64 != nullptr) {
+    const int st = refine_move<T>(s, c, ltr, Rr, Cc, g, G, grp, smem);
+    if (st == 0) return false;
+    if (st == 1) {
+      clk.lap(s.prof, PF_MOVE_GEMM);
+      return true;
+    }
+  }
   const int r = s.ctr[CT_RANK];
   if (ltr) {
     // M_c = Y^T S^-1 (4cl x r);  Rm = S W_perm (r x cr)

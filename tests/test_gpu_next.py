@@ -82,6 +82,7 @@ def test_loglin_noise_fit_and_fallback_on_gpu_levels():
     ofid = np.array([o.fidelity for o in orc])
     lam = np.array(w.factors) * w.noise["dep"]
     target = w.noise["dep"]
+    assert np.max(np.abs(vals - oval)) < 1e-10
     methods = set()
     for i in range(len(w.observables)):
         v, coef, used, mu = nze.extrapolate(lam[1:], vals[1:, i], fid[1:], target,
@@ -91,10 +92,13 @@ def test_loglin_noise_fit_and_fallback_on_gpu_levels():
         assert abs(v - vo) < 1e-9 and np.array_equal(used, uo)
         methods.add(mo)
         # criterion 2 with threshold 1 excludes every point: the direct
-        # exponential fit on all four levels takes over
+        # exponential fit on all four levels takes over.  Four points of a
+        # nearly linear decay leave the exponential's rate poorly determined,
+        # so the library's and the oracle's fits are compared on the same
+        # (GPU) values; the values themselves agree with the oracle's above.
         v2, _, used2, mu2 = nze.extrapolate(lam, vals[:, i], fid, target,
                                             nze.NZE_LOGLIN_W, small=1.0)
-        vo2, mo2, _, _ = fits.nzne(lam, oval[:, i], ofid, target, small=1.0)
+        vo2, mo2, _, _ = fits.nzne(lam, vals[:, i], fid, target, small=1.0)
         assert mu2 == nze.NZE_EXP3 and mo2 == "exp3"
         assert abs(v2 - vo2) < 1e-7 * max(1.0, abs(vo2))
     _say(f"methods used: {sorted(methods)}")

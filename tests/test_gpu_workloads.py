@@ -33,15 +33,9 @@ def _golden(name):
         return json.load(f)
 
 
-_MIXED_LONG = pytest.param(
-    nze.NZE_MIXED, MIXED_TOL, marks=pytest.mark.xfail(
-        reason="mixed path measured 0.8e-5 .. 3.3e-5 on these long truncated runs "
-               "(float32 accumulator and row rounding); refinement pending",
-        strict=False))
-
-
 @pytest.mark.parametrize("chi", [64, 128, 256])
-@pytest.mark.parametrize("precision,tol", [(nze.NZE_FP64, FP64_TOL), _MIXED_LONG])
+@pytest.mark.parametrize("precision,tol", [(nze.NZE_FP64, FP64_TOL),
+                                           (nze.NZE_MIXED, MIXED_TOL)])
 def test_precision_workload_n32(chi, precision, tol):
     # n = 32, depth 20, depolarizing 1e-3 then amplitude damping 5e-4, one
     # level: every <Z_i>, the emulation fidelity (relative) and the trace
@@ -66,7 +60,14 @@ def test_precision_workload_n32(chi, precision, tol):
     m.close()
 
 
-@pytest.mark.parametrize("precision,tol", [(nze.NZE_FP64, FP64_TOL), _MIXED_LONG])
+@pytest.mark.parametrize("precision,tol", [
+    (nze.NZE_FP64, FP64_TOL),
+    pytest.param(nze.NZE_MIXED, MIXED_TOL, marks=pytest.mark.xfail(
+        reason="mixed path: levels 0-3 and 5-7 within 5.2e-6, level 4 reaches 1.07e-5 on "
+               "<Z_46>: the float32 error random-walks to 2.5e-6 by layer 22 and the last two "
+               "layers (F 8e-10 -> 2e-11) amplify it fourfold; float64 shows the same "
+               "amplification at 4e-13 -> 7e-13", strict=False)),
+])
 def test_headline_job_all_layers(precision, tol):
     # n = 50, depth 24, eight levels (1 + 15 j / 7) x 1e-3, chi = 256, all
     # levels in one launch per layer: every <Z_i> and <X_1 X_2> at the levels
@@ -92,9 +93,7 @@ def test_headline_job_all_layers(precision, tol):
         _say(f"  level {j}: max|dO|={err:.3e} rel dF={ferr:.3e} F={fid[j]:.4e} "
              f"min gap {ref['min_cut_gap']:.2e} cap hits {st[j]['cap_hits']}")
         assert err < tol
-        # the emulation fidelity is a product of 588 partial fidelities; each
-        # carries the path's relative rounding, so the bound scales with them
-        assert ferr < (tol if precision == nze.NZE_FP64 else 588 * 2e-6)
+        assert ferr < tol
     m.close()
 
 
