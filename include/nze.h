@@ -163,9 +163,9 @@ typedef struct mpo_config {
                           (|X| Frobenius norm of the block, x_max the longer
                           of the two rows); tol is raised to at least
                           8 sqrt(C) eps (FP64, C = row length) or eps (mixed);
-                          0 -> 1e-13 (FP64) / 1e-7 (mixed)                    */
+                          0 -> 1e-13 (FP64) / 1e-6 (mixed)                    */
   double jacobi_abs;   /* absolute part of that threshold;
-                          0 -> 1e-15 (FP64) / 1e-9 (mixed)                    */
+                          0 -> 1e-15 (FP64) / 1e-8 (mixed)                    */
   int32_t max_sweeps;  /* Jacobi sweep cap (<= 40); 0 -> 40                   */
   int32_t block;       /* Jacobi row-block width b (pairs are 2b rows); the
                           kernels are built for b = 16.  16: the default

@@ -63,10 +63,10 @@ def test_precision_workload_n32(chi, precision, tol):
 @pytest.mark.parametrize("precision,tol", [
     (nze.NZE_FP64, FP64_TOL),
     pytest.param(nze.NZE_MIXED, MIXED_TOL, marks=pytest.mark.xfail(
-        reason="mixed path: levels 0-3 and 5-7 within 5.2e-6, level 4 reaches 1.07e-5 on "
-               "<Z_46>: the float32 error random-walks to 2.5e-6 by layer 22 and the last two "
-               "layers (F 8e-10 -> 2e-11) amplify it fourfold; float64 shows the same "
-               "amplification at 4e-13 -> 7e-13", strict=False)),
+        reason="at F ~ 2e-11 the mixed path's float32 rounding random-walks to a few 1e-6 and the "
+               "last layers amplify it: with the default thresholds every level is within 5.3e-6, "
+               "but other thresholds (same refinement) scattered the worst level over 5e-6 .. "
+               "1.3e-5, so a pass here is not guaranteed by margin", strict=False)),
 ])
 def test_headline_job_all_layers(precision, tol):
     # n = 50, depth 24, eight levels (1 + 15 j / 7) x 1e-3, chi = 256, all
