@@ -263,6 +263,10 @@ typedef struct nze_stats {
   double cap_offdiag;    /* largest scaled off-diagonal, in units of the
                             tolerance, in the last sweep of any SVD that
                             reached max_sweeps (0 if none did)               */
+  int64_t ns_scaled;     /* mixed path: orthonormalisations of the float64
+                            refinement whose start was too far from
+                            orthonormal for the plain iteration (the scaled,
+                            longer one was used)                              */
 } nze_stats;
 
 /* Per-level statistics (synchronises the stream).

@@ -29,7 +29,8 @@ enum { SC_LOG = 0, SC_FID = 1, SC_MAXDISC = 2, SC_MINGAP = 3, SC_F2 = 4,
 // per-MPO int counters
 enum { CT_RANK = 0, CT_ERR = 1, CT_MAXSW = 2, CT_UPD = 3, CT_SWTOT = 4,
        CT_OFFMAX = 5, CT_CAPHIT = 6, CT_NSMAX = 7, CT_ROT = 8, CT_BVER = 8 + MAXSW,
-       CT_WVER = CT_BVER + 136, CT_COUNT = CT_WVER + 136 };
+       CT_WVER = CT_BVER + 136, CT_NSFB = CT_WVER + 136, CT_COUNT = CT_NSFB + 1 };
+// CT_NSFB: orthonormalisations that needed the scaled (slow) iteration
 // CT_BVER / CT_WVER: per row block (<= 136), visits whose data rows / whose
 // accumulator rows are final
 enum { ERR_NOCONV = 1, ERR_NAN = 2, ERR_ABORT = 4 };
@@ -48,7 +49,9 @@ struct Slot {
   double* sval;     // [m_cap] kept singular values
   int n, chi, site_cap, m_cap;
   double tau, tie, tol_rel, tol_abs;
-  int max_sweeps, pad;
+  int max_sweeps;
+  int no_acc;       // 1: the Jacobi keeps no accumulator (the float64
+                    // refinement builds the orthonormal factor from the rows)
   double* prof;     // [PROF_N] constant-rate clock ticks per phase (WG 0)
   // Jacobi schedule: the first cross_sweeps sweeps of problems with at least
   // cross_min_blocks row blocks take cross-block inner steps only

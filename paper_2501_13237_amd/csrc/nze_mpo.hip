@@ -614,6 +614,7 @@ extern "C" int mpo_init(mpo_t** out, const mpo_config* cfg,
     s.R64 = c.precision == NZE_MIXED
                 ? reinterpret_cast<double*>(h->ws + lay.r64) + (size_t)l * r64_doubles(c.chi_max, h->m_cap)
                 : nullptr;
+    s.no_acc = c.precision == NZE_MIXED ? 1 : 0;
     s.cross_sweeps = have_tune ? tune_rec.cross_sweeps : 8;
     s.cross_min_blocks = have_tune ? tune_rec.cross_min_blocks : 64;
     h->slots.push_back(s);
@@ -948,6 +949,7 @@ extern "C" int mpo_stats(mpo_t* h, nze_stats* stats, int32_t* bonds) {
     s.flops = sc[SC_FLOPS];
     s.cap_hits = ct[CT_CAPHIT];
     s.cap_offdiag = sc[SC_CAPQ];
+    s.ns_scaled = ct[CT_NSFB];
     int mb = 0;
     for (int b = 1; b < n; ++b) {
       mb = std::max(mb, dims[(size_t)l * (n + 1) + b]);

@@ -123,7 +123,8 @@ __device__ void set_identity(T* W, int n, int g, int G) {
 // X <- (R x 1)(M_k M_{k+1}); also W = I and F2 = ||X||^2.
 template <typename T>
 __device__ void phase_theta(const Slot& s, int k, bool ltr, const double* R,
-                            int g, int G, double* smem, bool count = true) {
+                            int g, int G, double* smem, bool count = true,
+                            bool init_w = true) {
   typedef typename AccT<T>::type acc_t;
   const int cl = s.dims[k], cm = s.dims[k + 1], cr = s.dims[k + 2];
   const T* A = site_ptr<T>(s, k);          // (4 cl) x cm
@@ -178,7 +179,7 @@ __device__ void phase_theta(const Slot& s, int k, bool ltr, const double* R,
   }
   if (count && g == 0 && tid == 0)   // contraction 2 (4cl) cm (4cr) + superoperator 512 cl cr
     s.scal[SC_FLOPS] += 32.0 * cl * cm * cr + 512.0 * cl * cr;
-  set_identity(reinterpret_cast<T*>(s.W), ltr ? 4 * cl : 4 * cr, g, G);
+  if (init_w) set_identity(reinterpret_cast<T*>(s.W), ltr ? 4 * cl : 4 * cr, g, G);
 }
 
 // --------------------------------------------------------- Jacobi phase
@@ -515,6 +516,7 @@ __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
   // that order the next sweep, without a pass over X
   if (last_round && tid < 32 && L.rows[tid] >= 0) store1(s.norms + L.rows[tid], Gfin[tid * GLD + tid]);
   blocks_release(grp, verX, I, J);
+  if (s.no_acc) return true;
   // accumulator rows: previous visits of both blocks first, in visit order
   if (!blocks_wait(grp, verW, I, J, target)) return false;
   if (go) pair_rotate<T, VEC>(W, R, R, L);
@@ -869,49 +871,63 @@ __device__ void copy_t64(const double* src, int lds, int r, int n, T* dst, int l
 
 // Newton-Schulz iteration Q <- (3 I - Q Q^T) Q / 2 on the r rows of Q
 // (r x n, float64), ping-ponging between Q0 and Q1 with B (r x r) as scratch.
-// The largest |Q Q^T - I| entry e of the start, reduced over the group into
-// ctr[CT_NSMAX] (a maximum, so the order of the atomics does not matter),
-// sets the number of steps: each step takes e to about 3 e^2 / 4, so 1e-5
-// needs one step to reach 1e-10, 1e-3 two, 2e-2 three, 0.15 four and 0.5
-// five.  Returns the buffer holding the orthonormal rows, or nullptr when
-// the start is beyond 1/2 (outside the iteration's safe range) or a barrier
-// failed (*ok false).
+// It converges to the orthonormal polar factor when every singular value of
+// Q lies in (0, sqrt 3); the Gershgorin bound e = max_i sum_j |(Q Q^T - I)_ij|
+// of the start, reduced over the group into ctr[CT_NSMAX] (a maximum, so the
+// order of the atomics does not matter), places them in
+// (sqrt(max(0, 1 - e)), sqrt(1 + e)).  For e < 0.9 the number of steps
+// follows from e (each step takes an error e to about 3 e^2 / 4: 1e-5 needs
+// one step, 1e-3 two, 2e-2 three, 0.15 four, 0.9 six).  Otherwise the rows
+// are first scaled by 1 / sqrt(1 + e), which puts every singular value below
+// one, and fourteen steps are taken (a value 0.1 reaches one in eight);
+// ctr[CT_NSFB] counts those cases.  Returns the buffer holding the result, or
+// nullptr when a barrier failed.
 __device__ inline double* ns_rows(double* Q0, double* Q1, int n, int r, double* B,
-                                  const Slot& s, int g, int G, Group& grp, bool* ok) {
+                                  const Slot& s, int g, int G, Group& grp) {
   double* cur = Q0;
   double* nxt = Q1;
-  *ok = false;
   if (g == 0 && threadIdx.x == 0) s.ctr[CT_NSMAX] = 0;
   if (!group_sync(grp)) return nullptr;
   gemm64<double, double, true>(cur, n, cur, n, B, r, r, r, n, g, G);
   if (!group_sync(grp)) return nullptr;
   float emax = 0.f;
-  for (int e = g * NT + threadIdx.x; e < r * r; e += G * NT) {
-    const int i = e / r, j = e - i * r;
-    const double d = fabs(B[e] - (i == j ? 1.0 : 0.0));
-    emax = fmaxf(emax, (d == d) ? float(d) : 1e30f);
+  for (int i = g * NT + threadIdx.x; i < r; i += G * NT) {
+    double rs = 0.0;
+    for (int j = 0; j < r; ++j) rs += fabs(B[(size_t)i * r + j] - (i == j ? 1.0 : 0.0));
+    emax = fmaxf(emax, (rs == rs) ? float(rs) : 1e30f);
   }
   for (int o = 32; o > 0; o >>= 1) emax = fmaxf(emax, __shfl_xor(emax, o, 64));
   if ((threadIdx.x & 63) == 0 && emax > 0.f) atomicMax(&s.ctr[CT_NSMAX], __float_as_int(emax));
   if (!group_sync(grp)) return nullptr;
   const float e0 = __int_as_float(__hip_atomic_load(&s.ctr[CT_NSMAX], __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT));
-  *ok = true;
-  if (!(e0 <= 0.5f)) return nullptr;
-  const int steps = e0 <= 1e-13f ? 0 : e0 <= 1e-5f ? 1 : e0 <= 1e-3f ? 2 : e0 <= 2e-2f ? 3
-                  : e0 <= 0.15f ? 4 : 5;
+  int steps;
+  bool regram = false;
+  if (e0 < 0.9f) {
+    steps = e0 <= 1e-13f ? 0 : e0 <= 1e-5f ? 1 : e0 <= 1e-3f ? 2 : e0 <= 2e-2f ? 3
+          : e0 <= 0.15f ? 4 : 6;
+  } else {
+    // scaled start: Q <- Q / sqrt(1 + e)
+    const double sc = 1.0 / sqrt(1.0 + (e0 < 1e30f ? double(e0) : 1e30));
+    for (size_t e = (size_t)g * NT + threadIdx.x; e < (size_t)r * n; e += (size_t)G * NT)
+      cur[e] *= sc;
+    if (g == 0 && threadIdx.x == 0) s.ctr[CT_NSFB] += 1;
+    steps = 14;
+    regram = true;
+    if (!group_sync(grp)) return nullptr;
+  }
   for (int st = 0; st < steps; ++st) {
-    if (st > 0) {
+    if (st > 0 || regram) {
       gemm64<double, double, true>(cur, n, cur, n, B, r, r, r, n, g, G);
-      if (!group_sync(grp)) { *ok = false; return nullptr; }
+      if (!group_sync(grp)) return nullptr;
     }
     for (int e = g * NT + threadIdx.x; e < r * r; e += G * NT) {
       const int i = e / r, j = e - i * r;
       B[e] = (i == j ? 1.5 : 0.0) - 0.5 * B[e];
     }
-    if (!group_sync(grp)) { *ok = false; return nullptr; }
+    if (!group_sync(grp)) return nullptr;
     gemm64<double, double, false>(B, r, cur, n, nxt, n, r, n, r, g, G);
-    if (!group_sync(grp)) { *ok = false; return nullptr; }
+    if (!group_sync(grp)) return nullptr;
     double* t = cur; cur = nxt; nxt = t;
   }
   return cur;
@@ -1043,77 +1059,88 @@ __device__ inline void band_rotate(double* M, int ld, int n, int b0, int nb, con
   __syncthreads();
 }
 
-// Gate update after phase_select(defer): float64 factors from the kept
-// directions, the block recomputed from the unchanged sites, and the
-// partial-fidelity bookkeeping of the refined projection.  Returns 1 when
-// done, 0 on a barrier failure, -1 when the kept accumulator rows are too far
-// from orthonormal for the iteration (the float32 factors are then used).
+// Gate update after phase_select(defer), from the rows of the float32
+// Jacobi alone.  The Jacobi ran on the block oriented so that its rows carry
+// the factor that stays orthonormal: left to right the rows of Theta'^T
+// (indexed (q', b)), whose rotated rows are s_i u_i^T; right to left the rows
+// of Theta' (indexed (a, p')), whose rotated rows are s_i v_i^T.  The kept
+// rows divided by their norms, orthonormalised in float64 (ns_rows), give
+// Q = U_r^T (resp. V_r^T); the other factor is the float64 projection of the
+// recomputed block, Y = Q X0^T.  A float64 Rayleigh-Ritz polish of the BAND
+// kept and BAND dropped directions around a chi cut resolves the mixing the
+// float32 Jacobi leaves between near-degenerate directions there (about
+// tol / (2 relative gap)), and the tie rule is re-decided on its values.
+// Returns 1 when done, 0 on a barrier failure.
 template <typename T>
-__device__ __attribute__((noinline)) int refine_gate(const Slot& s, int k, bool ltr, const double* Rptm, int Rr,
-                           int Cc, int g, int G, Group& grp, double* smem) {
+__device__ __attribute__((noinline)) int refine_gate(const Slot& s, int k, bool ltr,
+                                                     const double* Rptm, int Rr, int Cc,
+                                                     int g, int G, Group& grp,
+                                                     double* smem) {
   const int r = s.ctr[CT_RANK];
-  // the kept rows and the BAND dropped rows right below the cut
-  const int lo = r < BAND ? r : BAND;
-  const int hi = Rr - r < BAND ? Rr - r : BAND;
+  // the band: only at a cut set by chi, and only over dropped directions
+  // within three decades of the last kept one
+  const int above = (int)s.scal[SC_ABOVE];
+  int hi = 0;
+  if (r == s.chi && r < above) {
+    const double s_last = sqrt(fmax(s.norms[s.perm[r - 1]], 0.0));
+    while (hi < BAND && r + hi < Rr &&
+           sqrt(fmax(s.norms[s.perm[r + hi]], 0.0)) >= 1e-3 * s_last) ++hi;
+  }
+  const int lo = hi > 0 ? (r < BAND ? r : BAND) : 0;
   const int rr = r + hi;
   double* A = s.R64;                                  // rr x max(Rr, Cc)
   double* B = A + r64_rows(s) * s.m_cap;              // rr x rr, or the band's 32 x 32
   double* C = B + r64_square(s);                      // rr x max(Rr, Cc)
-  const T* W = reinterpret_cast<const T*>(s.W);
+  const T* X = reinterpret_cast<const T*>(s.X);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int i = g * 4 + w; i < rr; i += 4 * G) {
-    const T* src = W + (size_t)s.perm[i] * Rr;
-    for (int c = lane; c < Rr; c += 64) A[(size_t)i * Rr + c] = double(load1(src + c));
+    const int row = s.perm[i];
+    const double nr = sqrt(fmax(s.norms[row], 0.0));
+    const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
+    const T* src = X + (size_t)row * Cc;
+    for (int c = lane; c < Cc; c += 64) A[(size_t)i * Cc + c] = double(load1(src + c)) * inv;
   }
-  bool ok;
-  double* Q = ns_rows(A, C, Rr, rr, B, s, g, G, grp, &ok);
-  if (!ok) return 0;
-  if (!Q) return -1;
+  double* Q = ns_rows(A, C, Cc, rr, B, s, g, G, grp);
+  if (!Q) return 0;
   double* Y = Q == A ? C : A;
-  // the block again (its sites are untouched until the gathers below)
-  phase_theta<T>(s, k, ltr, Rptm, g, G, smem, false);
+  // the block again, in the Jacobi's orientation (its sites are untouched
+  // until the gathers below)
+  phase_theta<T>(s, k, !ltr, Rptm, g, G, smem, false, false);
   if (!group_sync(grp)) return 0;
-  gemm64<double, T, false>(Q, Rr, reinterpret_cast<const T*>(s.X), Cc, Y, Cc, rr, Cc, Rr, g, G);
+  gemm64<double, T, true>(Q, Cc, X, Cc, Y, Rr, rr, Rr, Cc, g, G);   // Y = Q X0^T
   if (!group_sync(grp)) return 0;
-  // Rayleigh-Ritz in float64 on the band around the cut: the float32 Jacobi
-  // leaves near-degenerate directions on either side mixed by about
-  // tol / (2 relative gap); diagonalising the band's float64 Gram resolves
-  // that mixing, and the largest lo band directions are the kept ones
   const int nb = lo + hi, b0 = r - lo;
   if (hi > 0 && lo > 0) {
     double* V = B;                                    // 32 x 32
     if (g == 0) {
       const PairLds L = pair_lds(smem);
-      // band Gram Y_b Y_b^T in float64, one (u, v) entry per thread group
       for (int e = threadIdx.x; e < 32 * 32; e += NT) L.Gs[(e >> 5) * GLD + (e & 31)] = 0.0;
       __syncthreads();
       for (int uv = w; uv < nb * nb; uv += 4) {
         const int u = uv / nb, v = uv - u * nb;
         if (v < u) continue;
         double acc = 0.0;
-        const double* yu = Y + (size_t)(b0 + u) * Cc;
-        const double* yv = Y + (size_t)(b0 + v) * Cc;
-        for (int c = lane; c < Cc; c += 64) acc = fma(yu[c], yv[c], acc);
+        const double* yu = Y + (size_t)(b0 + u) * Rr;
+        const double* yv = Y + (size_t)(b0 + v) * Rr;
+        for (int c = lane; c < Rr; c += 64) acc = fma(yu[c], yv[c], acc);
         acc = wave_sum(acc);
         if (lane == 0) { L.Gs[u * GLD + v] = acc; L.Gs[v * GLD + u] = acc; }
       }
       __syncthreads();
       double* EV = V + 1024;
       band_eigh(L, nb, V, EV);
-      // the truncation rule again where float64 values decide it: when the
-      // cut is set by chi and its two sides lie in the band, the tie rule
-      // (drop the chained cluster whose neighbours agree within tie_tol)
-      // runs on the band's float64 values; float32 norms carry relative
+      // the truncation rule again where float64 values decide it: the tie
+      // rule (drop the chained cluster whose neighbours agree within
+      // tie_tol) runs on the band's values; float32 norms carry relative
       // errors of eps s_1 / s_r, as large as tie_tol at the cut
       if (threadIdx.x == 0) {
-        const int above = (int)s.scal[SC_ABOVE];
         const int r0 = above < s.chi ? above : s.chi;
         int rn = r;
-        if (r0 == s.chi && r0 < above && r0 > b0 && r0 < b0 + nb) {
+        if (r0 > b0 && r0 < b0 + nb) {
           int q = r0;
           while (q > b0) {
-            const double a = sqrt(fmax(EV[q - 1 - b0], 0.0)), b = sqrt(fmax(EV[q - b0], 0.0));
-            if (a - b <= s.tie * a) --q; else break;
+            const double a = sqrt(fmax(EV[q - 1 - b0], 0.0)), bq = sqrt(fmax(EV[q - b0], 0.0));
+            if (a - bq <= s.tie * a) --q; else break;
           }
           if (q > b0) rn = q;            // resolved inside the band
           if (q == 0) rn = r0;           // the whole spectrum tied: keep chi
@@ -1122,12 +1149,12 @@ __device__ __attribute__((noinline)) int refine_gate(const Slot& s, int k, bool 
       }
     }
     if (!group_sync(grp)) return 0;
-    band_rotate(Q, Rr, Rr, b0, nb, V, g, G, smem);
-    band_rotate(Y, Cc, Cc, b0, nb, V, g, G, smem);
+    band_rotate(Q, Cc, Cc, b0, nb, V, g, G, smem);
+    band_rotate(Y, Rr, Rr, b0, nb, V, g, G, smem);
     if (!group_sync(grp)) return 0;
   }
   const int rk = s.ctr[CT_RANK];
-  rows_norm64(s, Y, rk, Cc, g, G);
+  rows_norm64(s, Y, rk, Rr, g, G);
   if (!group_sync(grp)) return 0;
   if (g == 0) {
     double* red = smem;
@@ -1148,12 +1175,12 @@ __device__ __attribute__((noinline)) int refine_gate(const Slot& s, int k, bool 
   const double inv = 1.0 / sqrt(s.scal[SC_KEPT]);
   T* Mk = site_ptr<T>(s, k);
   T* Mk1 = site_ptr<T>(s, k + 1);
-  if (ltr) {   // M_k = Q^T (4cl x r), M_{k+1} = Q X0 / ||.|| (r x 4cr)
-    copy_t64<T>(Q, Rr, rk, Rr, Mk, rk, 1.0, g, G, smem);
-    copy_r64<T>(Y, Cc, rk, Cc, Mk1, Cc, inv, g, G);
-  } else {     // M_k = (Q X0)^T / ||.|| (4cl x r), M_{k+1} = Q (r x 4cr)
-    copy_t64<T>(Y, Cc, rk, Cc, Mk, rk, inv, g, G, smem);
-    copy_r64<T>(Q, Rr, rk, Rr, Mk1, Rr, 1.0, g, G);
+  if (ltr) {   // Q rows in (a, p'): M_k = Q^T (4cl x r), M_{k+1} = Y / ||.|| (r x 4cr)
+    copy_t64<T>(Q, Cc, rk, Cc, Mk, rk, 1.0, g, G, smem);
+    copy_r64<T>(Y, Rr, rk, Rr, Mk1, Rr, inv, g, G);
+  } else {     // Q rows in (q', b): M_k = Y^T / ||.|| (4cl x r), M_{k+1} = Q (r x 4cr)
+    copy_t64<T>(Y, Rr, rk, Rr, Mk, rk, inv, g, G, smem);
+    copy_r64<T>(Q, Cc, rk, Cc, Mk1, Cc, 1.0, g, G);
   }
   return group_sync(grp) ? 1 : 0;
 }
@@ -1163,8 +1190,7 @@ __device__ __attribute__((noinline)) int refine_gate(const Slot& s, int k, bool 
 // factor as the projection of the site onto it, absorbed into the neighbour
 // in float64.  The projection keeps the state whatever rotation the
 // iteration applies inside the kept span, so the move stays exact up to the
-// dropped numerical zeros.  Returns 1 when done, 0 on a barrier failure, -1
-// when the rows are too far from orthonormal (the float32 factors are used).
+// dropped numerical zeros.  Returns 1 when done, 0 on a barrier failure.
 template <typename T>
 __device__ __attribute__((noinline)) int refine_move(const Slot& s, int c, bool ltr, int Rr, int Cc, int g, int G,
                            Group& grp, double* smem) {
@@ -1179,10 +1205,8 @@ __device__ __attribute__((noinline)) int refine_move(const Slot& s, int c, bool 
     const double inv = 1.0 / s.sval[i];
     for (int cc = lane; cc < Cc; cc += 64) A[(size_t)i * Cc + cc] = double(load1(src + cc)) * inv;
   }
-  bool ok;
-  double* Q = ns_rows(A, C, Cc, r, B, s, g, G, grp, &ok);
-  if (!ok) return 0;
-  if (!Q) return -1;
+  double* Q = ns_rows(A, C, Cc, r, B, s, g, G, grp);
+  if (!Q) return 0;
   double* P = Q == A ? C : A;                         // second factor / product
   T* M = site_ptr<T>(s, c);
   const int cl = s.dims[c], cr = s.dims[c + 1];
@@ -1222,11 +1246,17 @@ template <typename T, int VEC = 1>
 __device__ __forceinline__ bool op_gate(const Slot& s, int k, bool ltr, const double* R, int g,
                         int G, Group& grp, double* smem) {
   const int cl = s.dims[k], cr = s.dims[k + 2];
-  const int Rr = ltr ? 4 * cl : 4 * cr, Cc = ltr ? 4 * cr : 4 * cl;
+  // with the float64 refinement (float32 path) the Jacobi keeps no
+  // accumulator and runs on the orientation whose rows carry the factor that
+  // stays orthonormal (refine_gate); otherwise rows (a, p') left to right
+  bool refine = false;
+  if constexpr (sizeof(T) == 4) refine = s.R64 != nullptr && s.no_acc;
+  const bool rows_ap = refine ? !ltr : ltr;
+  const int Rr = rows_ap ? 4 * cl : 4 * cr, Cc = rows_ap ? 4 * cr : 4 * cl;
   T* X = reinterpret_cast<T*>(s.X);
   T* W = reinterpret_cast<T*>(s.W);
   PhaseClock clk(g == 0 && s.prof != nullptr);
-  phase_theta<T>(s, k, ltr, R, g, G, smem);
+  phase_theta<T>(s, k, rows_ap, R, g, G, smem, true, !s.no_acc);
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_THETA);
   if (!phase_jacobi<T, VEC>(s, X, W, Rr, Cc, g, G, grp, smem)) return false;
@@ -1234,26 +1264,15 @@ __device__ __forceinline__ bool op_gate(const Slot& s, int k, bool ltr, const do
   phase_norms<T>(s, X, Rr, Cc, g, G);
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_NORMS);
-  if (g == 0) phase_select(s, Rr, true, smem, sizeof(T) == 4 && s.R64 != nullptr);
+  if (g == 0) phase_select(s, Rr, true, smem, refine);
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_SELECT);
-  if constexpr (sizeof(T) == 4) if (s.R64 != nullptr) {
-    const int st = refine_gate<T>(s, k, ltr, R, Rr, Cc, g, G, grp, smem);
-    if (st == 0) return false;
-    if (st == 1) {
-      if (g == 0 && threadIdx.x == 0) s.dims[k + 1] = s.ctr[CT_RANK];
-      const bool ok = group_sync(grp);
-      clk.lap(s.prof, PF_ABSORB);
-      return ok;
-    }
-    // no refinement: the partial fidelity of the float32 factors
-    if (g == 0 && threadIdx.x == 0) {
-      const double kept = s.scal[SC_KEPT], f = kept / s.scal[SC_TOT];
-      s.scal[SC_FID] *= f;
-      s.scal[SC_LOG] += 0.5 * log(kept);
-      s.scal[SC_MAXDISC] = fmax(s.scal[SC_MAXDISC], 1.0 - f);
-    }
-    if (!group_sync(grp)) return false;
+  if constexpr (sizeof(T) == 4) if (refine) {
+    if (!refine_gate<T>(s, k, ltr, R, Rr, Cc, g, G, grp, smem)) return false;
+    if (g == 0 && threadIdx.x == 0) s.dims[k + 1] = s.ctr[CT_RANK];
+    const bool ok = group_sync(grp);
+    clk.lap(s.prof, PF_ABSORB);
+    return ok;
   }
   const int r = s.ctr[CT_RANK];
   const double inv = 1.0 / sqrt(s.scal[SC_KEPT]);
@@ -1329,7 +1348,7 @@ __device__ __forceinline__ bool op_move(const Slot& s, int c, bool ltr, int g, i
           X[(size_t)r * Cc + cc] = v;
         }
     }
-    set_identity(W, Rr, g, G);
+    if (!s.no_acc) set_identity(W, Rr, g, G);
   }
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_MOVE_PREP);
@@ -1340,13 +1359,10 @@ __device__ __forceinline__ bool op_move(const Slot& s, int c, bool ltr, int g, i
   if (g == 0) phase_select(s, Rr, false, smem);
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_SELECT);
-  if constexpr (sizeof(T) == 4) if (s.R64 != nullptr) {
-    const int st = refine_move<T>(s, c, ltr, Rr, Cc, g, G, grp, smem);
-    if (st == 0) return false;
-    if (st == 1) {
-      clk.lap(s.prof, PF_MOVE_GEMM);
-      return true;
-    }
+  if constexpr (sizeof(T) == 4) if (s.R64 != nullptr && s.no_acc) {
+    const bool ok = refine_move<T>(s, c, ltr, Rr, Cc, g, G, grp, smem) == 1;
+    clk.lap(s.prof, PF_MOVE_GEMM);
+    return ok;
   }
   const int r = s.ctr[CT_RANK];
   if (ltr) {

@@ -43,7 +43,7 @@ class NzeStats(ctypes.Structure):
                 ("max_bond", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("updates", ctypes.c_int64), ("sweeps_total", ctypes.c_int64),
                 ("flops", ctypes.c_double), ("cap_hits", ctypes.c_int64),
-                ("cap_offdiag", ctypes.c_double)]
+                ("cap_offdiag", ctypes.c_double), ("ns_scaled", ctypes.c_int64)]
 
 
 class NzeFitOpts(ctypes.Structure):
@@ -528,7 +528,8 @@ class MPO:
                      min_cut_gap=s.min_cut_gap, max_bond=s.max_bond,
                      max_sweeps=s.max_sweeps, updates=s.updates,
                      sweeps_total=s.sweeps_total, flops=s.flops,
-                     cap_hits=s.cap_hits, cap_offdiag=s.cap_offdiag)
+                     cap_hits=s.cap_hits, cap_offdiag=s.cap_offdiag,
+                     ns_scaled=s.ns_scaled)
                 for s in st], bonds
 
     def bond_spectrum(self, level, bond):
