@@ -13,11 +13,15 @@ lambda_j = (1 + 15 j / 7) p0, chi = 256; observables <Z_25>, <X_1 X_2>.
 588 gates x 8 levels = 4704 two-site updates per job.
 
 Prints one JSON line (rank 0).  `value` is two-site updates/s of the mixed
-(float32 MFMA) path; the plain float64 path is timed beside it.  Also
-reported: p50/p99 job latency of the serving loop on a short Poisson stream
-of mixed jobs, steady-state saturated updates at batch sizes 1-64, the NZNE
-error of the n = 8 workload against dense values, and the oracle on the host
-cores.
+path (float32 MFMA Jacobi, float64 refinement); the plain float64 path is
+timed beside it, and both paths' readouts are compared with the stored
+float64 oracle runs of the same job.  Also reported: p50/p99 job latency of
+the serving loop on a Poisson stream of mixed jobs at the offered 20 jobs/s
+(overload) and at 70 % of the completion rate it measured (sustainable), the
+NZNE error of the n = 8 workload against dense values, and the oracle on the
+host cores (all threads, and one thread).  Legs after the timed steps run
+only while the run stays inside --budget-s.  Steady-state saturated updates at
+several batch sizes are measured with --saturated-batches.
 """
 import argparse
 import json
@@ -218,14 +222,28 @@ def lattice_run(nze, workloads, rows, cols, rounds, chi, levels=8, seed=0):
             "fidelity_min": float(min(x["fidelity"] for x in st))}
 
 
-def cpu_baseline(w, layers, timed_layer=5, budget_s=40.0):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, layers, timed_layer=5, budget_s=30.0, one_thread_updates=3):
     """The oracle on noise level 1: evolve the first layers (bonds grow to
-    chi), then time one layer whose bonds are saturated."""
+    chi), then time one layer whose bonds are saturated with every host
+    thread, and the first updates of the next layer with one thread."""
+    from threadpoolctl import threadpool_limits
     from oracle import mpo as ompo
     from oracle import ptm
     nz = ptm.Noise(**w.noise)
     m = ompo.PauliMPO(w.n, w.chi)
     t_start = time.perf_counter()
+    t = 0
     for t, (ls, us) in enumerate(layers):
         ptms = [ptm.ptm_noisy_gate(U, nz) for U in us]
         t0 = time.perf_counter()
@@ -234,12 +252,28 @@ def cpu_baseline(w, layers, timed_layer=5, budget_s=40.0):
         if t >= timed_layer or time.perf_counter() - t_start > budget_s:
             break
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # one thread: gates from the middle of the next layer (saturated bonds),
+    # in its zig-zag order, after an untimed centre move to the first of them
+    nls, nus = layers[t + 1]
+    ltr = nls[0] % 2 == 0
+    mid = len(nls) // 2
+    order = (list(range(mid, mid + one_thread_updates)) if ltr
+             else list(range(mid, mid - one_thread_updates, -1)))
+    m.move_centre(nls[order[0]] if ltr else nls[order[0]] + 1)
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        for i in order:
+            m.apply_gate(nls[i], ptm.ptm_noisy_gate(nus[i], nz), ltr)
+        dt1 = time.perf_counter() - t1
     return {"value": len(ls) / dt, "unit": "updates/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "one_thread_updates_per_s": len(order) / dt1,
             "sample": (f"CPU float64 oracle (NumPy/LAPACK) on noise level 1 "
                        f"of {len(w.factors)}: layers 1-{t} evolved untimed, "
-                       f"layer {t + 1} timed ({len(ls)} updates in "
-                       f"{dt:.2f} s, bonds up to {max(m.bond_dims())})")}
+                       f"layer {t + 1} timed with {cores} threads ({len(ls)} updates "
+                       f"in {dt:.2f} s, bonds up to {max(m.bond_dims())}), then "
+                       f"{len(order)} updates from the middle of layer {t + 2} "
+                       f"with one thread in {dt1:.2f} s")}
 
 
 def serve_jobs(count, seed, workloads, nze):
@@ -353,7 +387,29 @@ def extrapolation_error(nze, workloads):
     return out
 
 
+def oracle_error(vals, fid, precision_name):
+    """The job's readout against the stored float64 oracle runs of the same
+    workload (tests/golden/n50_d24_oracle.json, written by the oracle): max
+    |d<O>| over the two observables and every level, max relative dF."""
+    path = os.path.join(ROOT, "tests", "golden", "n50_d24_oracle.json")
+    try:
+        with open(path) as f:
+            g = json.load(f)
+    except OSError:
+        return None
+    names = g["observables"]
+    idx = [names.index("I" * 25 + "Z" + "I" * 24), names.index("IXX" + "I" * 47)]
+    errs, ferr = [], []
+    for key, ref in g["levels"].items():
+        j = int(key)
+        errs.append(max(abs(vals[j][o] - ref["values"][i]) for o, i in enumerate(idx)))
+        ferr.append(abs(fid[j] / ref["fidelity"] - 1.0))
+    return {"path": precision_name, "levels": len(errs),
+            "max_abs_obs": float(max(errs)), "max_rel_fidelity": float(max(ferr))}
+
+
 def main():
+    t_start = time.perf_counter()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
@@ -362,16 +418,23 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--depth", type=int, default=None,
                     help="override the depth (diagnostics only)")
-    ap.add_argument("--serve", type=int, default=8,
+    ap.add_argument("--serve", type=int, default=10,
                     help="also run the serving loop on this many jobs "
                          "(0 to skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0)
-    ap.add_argument("--serve-sustainable-rate", type=float, default=0.0)
+    ap.add_argument("--serve-sustainable-rate", type=float, default=-1.0,
+                    help="offered rate of the second serving leg; -1: 70 %% of "
+                         "the completion rate measured in the first leg; 0: skip")
+    ap.add_argument("--serve-sustainable-jobs", type=int, default=6)
+    ap.add_argument("--budget-s", type=float, default=570.0,
+                    help="wall-time budget of the whole run: legs after the "
+                         "timed steps are skipped (and say so) when their "
+                         "estimated time does not fit")
     ap.add_argument("--no-extrapolation-error", action="store_true",
                     help="skip the n=8 extrapolation-error leg (profiling runs)")
     ap.add_argument("--skip-main", action="store_true",
                     help="only the serving runs")
-    ap.add_argument("--saturated-batches", default="1,8,32,64",
+    ap.add_argument("--saturated-batches", default="",
                     help="batch sizes of the saturated-update microbenchmark "
                          "(comma list; empty to skip)")
     ap.add_argument("--lattice", default="",
@@ -461,6 +524,9 @@ def main():
         "saturated_layers": saturated_rate(layers, layer_ms, len(w.factors)),
         "fidelity": [float(x) for x in fid],
         "jacobi_sweeps_total": int(sum(s["sweeps_total"] for s in stats)),
+        "cap_hits": int(sum(s["cap_hits"] for s in stats)),
+        "ns_scaled": int(sum(s["ns_scaled"] for s in stats)),
+        "error_vs_oracle": oracle_error(vals, fid, "mixed"),
         "extrapolation": {str(k): v for k, v in fits.items()},
     }
     if args.fp64_steps > 0:
@@ -476,14 +542,41 @@ def main():
         out["speedup_mixed_vs_fp64"] = value / v64
         out["mixed_vs_fp64_max_abs_obs"] = float(np.max(np.abs(vals - vals64)))
         out["mixed_vs_fp64_max_rel_fid"] = float(np.max(np.abs(fid - fid64) / fid64))
-    # the serving and saturated-batch legs are reported beside the headline;
-    # an error in one of them is reported in its field, not raised
+        out["fp64"]["error_vs_oracle"] = oracle_error(vals64, fid64, "fp64")
+    job_s = dt / args.steps
+
+    def fits(est_s):
+        return time.perf_counter() - t_start + est_s <= args.budget_s
+
+    # the serving legs are reported beside the headline; an error in one of
+    # them is reported in its field, not raised
     if args.serve:
-        try:
-            out["serving"] = serve_run(nze, serve_jobs(args.serve, 1, workloads, nze),
-                                       args.serve_rate, 1, nze.NZE_MIXED)
-        except Exception as e:  # noqa: BLE001
-            out["serving"] = {"error": repr(e)}
+        # a job of the mix is on average about a third of the n = 50 job
+        est = args.serve * job_s * 0.35 + 10.0
+        if not fits(est):
+            out["serving"] = {"skipped": f"time budget ({est:.0f} s estimated)"}
+        else:
+            try:
+                jobs = serve_jobs(args.serve, 1, workloads, nze)
+                out["serving"] = serve_run(nze, jobs, args.serve_rate, 1, nze.NZE_MIXED)
+            except Exception as e:  # noqa: BLE001
+                out["serving"] = {"error": repr(e)}
+        sus = args.serve_sustainable_rate
+        cap = out["serving"].get("completed_jobs_per_s") if isinstance(out["serving"], dict) else None
+        if sus < 0:
+            sus = 0.7 * cap if cap else 0.0
+        if sus > 0:
+            k = args.serve_sustainable_jobs
+            est = k / sus + 0.5 * k * job_s * 0.35 + 10.0
+            if not fits(est):
+                out["serving_sustainable"] = {"skipped": f"time budget ({est:.0f} s estimated)",
+                                              "offered_rate_jobs_per_s": sus}
+            else:
+                try:
+                    jobs = serve_jobs(k, 2, workloads, nze)
+                    out["serving_sustainable"] = serve_run(nze, jobs, sus, 2, nze.NZE_MIXED)
+                except Exception as e:  # noqa: BLE001
+                    out["serving_sustainable"] = {"error": repr(e)}
     if args.saturated_batches:
         try:
             out["saturated_batch"] = saturated_batches(
@@ -499,7 +592,11 @@ def main():
     if not args.no_extrapolation_error:
         out["extrapolation_error_n8"] = extrapolation_error(nze, workloads)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, layers)
+        if fits(45.0):
+            out["cpu_baseline"] = cpu_baseline(w, layers)
+        else:
+            out["cpu_baseline"] = {"skipped": "time budget"}
+    out["wall_s"] = time.perf_counter() - t_start
     print(json.dumps(out), flush=True)
 
 
