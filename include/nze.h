@@ -163,9 +163,9 @@ typedef struct mpo_config {
                           (|X| Frobenius norm of the block, x_max the longer
                           of the two rows); tol is raised to at least
                           8 sqrt(C) eps (FP64, C = row length) or eps (mixed);
-                          0 -> 1e-13 (FP64) / 1e-6 (mixed)                    */
+                          0 -> 1e-13 (FP64) / 3e-7 (mixed)                    */
   double jacobi_abs;   /* absolute part of that threshold;
-                          0 -> 1e-15 (FP64) / 1e-8 (mixed)                    */
+                          0 -> 1e-15 (FP64) / 1e-9 (mixed)                    */
   int32_t max_sweeps;  /* Jacobi sweep cap (<= 40); 0 -> 40                   */
   int32_t block;       /* Jacobi row-block width b (pairs are 2b rows); the
                           kernels are built for b = 16.  16: the default
@@ -254,8 +254,10 @@ typedef struct nze_stats {
                             32 cl cm cr + superoperator 512 cl cr per update;
                             per Jacobi sweep on R rows of length C,
                             4 R^2 (2C + R) (block Grams plus rotation of the
-                            data and of the accumulator); centre-move
-                            absorption 8 r cr c2                             */
+                            data and of the accumulator; 8 R^2 C in the mixed
+                            path, which keeps no accumulator); centre-move
+                            absorption 8 r cr c2.  The float64 refinement of
+                            the mixed path is not counted                    */
   int64_t cap_hits;      /* SVDs that reached max_sweeps while every pair was
                             within 1000x the tolerance (the rounding floor);
                             beyond that mpo_expect/mpo_sync report

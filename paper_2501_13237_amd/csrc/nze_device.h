@@ -69,8 +69,8 @@ enum { PF_THETA = 0, PF_GRAM, PF_CHECK, PF_EIGH, PF_ROTX, PF_ROTW, PF_WAIT,
 struct PhaseClock {
   bool on;
   uint64_t t;
-  __device__ PhaseClock(bool active) : on(active), t(active ? wall_clock64() : 0) {}
-  __device__ void lap(double* prof, int slot) {
+  __device__ __forceinline__ PhaseClock(bool active) : on(active), t(active ? wall_clock64() : 0) {}
+  __device__ __forceinline__ void lap(double* prof, int slot) {
     if (!on) return;
     const uint64_t now = wall_clock64();
     if (threadIdx.x == 0) prof[slot] += double(now - t);

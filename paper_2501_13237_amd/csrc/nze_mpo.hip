@@ -503,8 +503,8 @@ void fill_defaults(mpo_config& c) {
   const bool f64 = c.precision == NZE_FP64;
   if (c.trunc_tol <= 0) c.trunc_tol = f64 ? 1e-14 : 1e-7;
   if (c.tie_tol <= 0) c.tie_tol = f64 ? 1e-10 : 1e-5;
-  if (c.jacobi_tol <= 0) c.jacobi_tol = f64 ? 1e-13 : 1e-6;
-  if (c.jacobi_abs <= 0) c.jacobi_abs = f64 ? 1e-15 : 1e-8;
+  if (c.jacobi_tol <= 0) c.jacobi_tol = f64 ? 1e-13 : 3e-7;
+  if (c.jacobi_abs <= 0) c.jacobi_abs = f64 ? 1e-15 : 1e-9;
   if (c.max_sweeps <= 0) c.max_sweeps = MAXSW;   // dense near-degenerate spectra can need > 30
   if (c.block <= 0) c.block = BW;
 }

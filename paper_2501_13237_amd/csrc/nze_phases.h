@@ -34,7 +34,7 @@ __device__ inline T* site_ptr(const Slot& s, int k) {
 // 64x64-tile GEMM C = A B (row-major, all operands in path precision) over
 // the group's workgroups.  Wave w owns rows [16w, 16w+16) of a tile.
 template <typename T>
-__device__ void gemm_nn(const T* A, int lda, const T* B, int ldb, T* C, int ldc,
+__device__ __forceinline__ void gemm_nn(const T* A, int lda, const T* B, int ldb, T* C, int ldc,
                         int M, int N, int K, int g, int G) {
   typedef typename AccT<T>::type acc_t;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -65,7 +65,7 @@ __device__ void gemm_nn(const T* A, int lda, const T* B, int ldb, T* C, int ldc,
 // dst[a][i] = src[perm[i]][a] * scale_i  for a < na, i < r   (LDS transpose)
 // mode 0: scale = cst; 1: cst * sv[i]; 2: cst / sv[i]
 template <typename T>
-__device__ void gather_t(const T* src, int lds, const int* perm, int na, int r,
+__device__ __forceinline__ void gather_t(const T* src, int lds, const int* perm, int na, int r,
                          T* dst, int ldd, const double* sv, int mode,
                          double cst, int g, int G, double* smem) {
   T* tile = reinterpret_cast<T*>(smem);   // [32][33]
@@ -96,7 +96,7 @@ __device__ void gather_t(const T* src, int lds, const int* perm, int na, int r,
 
 // dst[i][c] = src[perm[i]][c] * scale_i  for i < r, c < nc
 template <typename T>
-__device__ void gather_r(const T* src, int lds, const int* perm, int r, int nc,
+__device__ __forceinline__ void gather_r(const T* src, int lds, const int* perm, int r, int nc,
                          T* dst, int ldd, const double* sv, int mode,
                          double cst, int g, int G) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -112,7 +112,7 @@ __device__ void gather_r(const T* src, int lds, const int* perm, int r, int nc,
 
 // W = I (n x n), distributed by rows.
 template <typename T>
-__device__ void set_identity(T* W, int n, int g, int G) {
+__device__ __forceinline__ void set_identity(T* W, int n, int g, int G) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int r = g * 4 + w; r < n; r += 4 * G)
     for (int c = lane; c < n; c += 64) W[(size_t)r * n + c] = T(r == c ? 1 : 0);
@@ -122,7 +122,7 @@ __device__ void set_identity(T* W, int n, int g, int G) {
 
 // X <- (R x 1)(M_k M_{k+1}); also W = I and F2 = ||X||^2.
 template <typename T>
-__device__ void phase_theta(const Slot& s, int k, bool ltr, const double* R,
+__device__ __forceinline__ void phase_theta(const Slot& s, int k, bool ltr, const double* R,
                             int g, int G, double* smem, bool count = true,
                             bool init_w = true) {
   typedef typename AccT<T>::type acc_t;
@@ -221,7 +221,7 @@ __device__ inline PairLds pair_lds(double* smem) {
 
 // Gs = X_rows X_rows^T (32 x 32) in float64 from MFMA partials.
 template <typename T>
-__device__ void pair_gram(const T* X, int ld, int C, const PairLds& L) {
+__device__ __forceinline__ void pair_gram(const T* X, int ld, int C, const PairLds& L) {
   typedef typename AccT<T>::type acc_t;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
@@ -377,7 +377,7 @@ __device__ const double* inner_eigh(const PairLds& L, bool cross_only) {
 
 // rows <- Q^T rows for the pair's 32 rows of M (ld, ncols), in place.
 template <typename T, int VEC = 1>
-__device__ void pair_rotate(T* M, int ld, int ncols, const PairLds& L) {
+__device__ __forceinline__ void pair_rotate(T* M, int ld, int ncols, const PairLds& L) {
   typedef typename AccT<T>::type acc_t;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
@@ -457,7 +457,7 @@ __device__ void pair_rotate(T* M, int ld, int ncols, const PairLds& L) {
 
 // One pair step of sweep `sw`: Gram, convergence test, inner solve, rotate.
 template <typename T, int VEC = 1>
-__device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
+__device__ __forceinline__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
                             int J, int nb, int sw, double F2, double* smem,
                             bool timed, const int* order, Group& grp,
                             int* verX, int* verW, int target, bool last_round,
@@ -527,7 +527,7 @@ __device__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
 
 // squared row norms in float64
 template <typename T>
-__device__ void phase_norms(const Slot& s, const T* X, int R, int C, int g,
+__device__ __forceinline__ void phase_norms(const Slot& s, const T* X, int R, int C, int g,
                             int G) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int r = g * 4 + w; r < R; r += 4 * G) {
@@ -544,7 +544,7 @@ __device__ void phase_norms(const Slot& s, const T* X, int R, int C, int g,
 
 // One workgroup: s.perm[0..R) = rows ordered by decreasing squared norm
 // (ties by index).  Bitonic sort of (key, index) pairs in LDS.
-__device__ void sort_rows(const Slot& s, int R, double* key, int* idx) {
+__device__ __forceinline__ void sort_rows(const Slot& s, int R, double* key, int* idx) {
   int N = 1;
   while (N < R) N <<= 1;
   const int tid = threadIdx.x;
@@ -669,7 +669,7 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
     if (rot == 0) { conv = true; break; }
   }
   if (g == 0 && threadIdx.x == 0) {
-    s.scal[SC_FLOPS] += 4.0 * sweeps * double(R) * double(R) * (2.0 * C + R);
+    s.scal[SC_FLOPS] += 4.0 * sweeps * double(R) * double(R) * (2.0 * C + (s.no_acc ? 0.0 : R));
     s.ctr[CT_SWTOT] += sweeps;
     if (sweeps > s.ctr[CT_MAXSW]) s.ctr[CT_MAXSW] = sweeps;
     if (!conv) {
@@ -687,7 +687,7 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
 // One workgroup: sort the squared norms, pick the rank, update fidelity and
 // log-scale.  gate: truncation rule with chi cap and tie rule; otherwise
 // (centre move) only numerical zeros (s_i <= tau s_1) are dropped.
-__device__ void phase_select(const Slot& s, int R, bool gate, double* smem,
+__device__ __forceinline__ void phase_select(const Slot& s, int R, bool gate, double* smem,
                              bool defer = false) {
   int N = 1;
   while (N < R) N <<= 1;
@@ -793,7 +793,7 @@ __device__ inline void load4_or0(const T* p, bool ok_all, int nvalid, double v[4
 }
 
 template <typename TA, typename TB, bool TB_T>
-__device__ void gemm64(const TA* A, int lda, const TB* B, int ldb, double* C, int ldc,
+__device__ __forceinline__ void gemm64(const TA* A, int lda, const TB* B, int ldb, double* C, int ldc,
                        int M, int N, int K, int g, int G) {
   typedef typename AccT<double>::type acc_t;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -839,7 +839,7 @@ __device__ void gemm64(const TA* A, int lda, const TB* B, int ldb, double* C, in
 
 // dst[i][c] = T(src[i][c] * scale), i < r, c < n
 template <typename T>
-__device__ void copy_r64(const double* src, int lds, int r, int n, T* dst, int ldd,
+__device__ __forceinline__ void copy_r64(const double* src, int lds, int r, int n, T* dst, int ldd,
                          double scale, int g, int G) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int i = g * 4 + w; i < r; i += 4 * G)
@@ -848,7 +848,7 @@ __device__ void copy_r64(const double* src, int lds, int r, int n, T* dst, int l
 
 // dst[a][i] = T(src[i][a] * scale), i < r, a < n (LDS transpose)
 template <typename T>
-__device__ void copy_t64(const double* src, int lds, int r, int n, T* dst, int ldd,
+__device__ __forceinline__ void copy_t64(const double* src, int lds, int r, int n, T* dst, int ldd,
                          double scale, int g, int G, double* smem) {
   double* tile = smem;   // [32][33]
   const int ta = (n + 31) / 32, ti = (r + 31) / 32;
@@ -964,7 +964,7 @@ __device__ inline size_t r64_square(const Slot& s) {
 // columns nb..31 are inert padding.  On return Vout (32 x 32, row u column a)
 // holds the eigenvector of column a in row u, columns in decreasing order of
 // their eigenvalue, and EVout[a] that eigenvalue.
-__device__ void band_eigh(const PairLds& L, int nb, double* Vout, double* EVout) {
+__device__ __forceinline__ void band_eigh(const PairLds& L, int nb, double* Vout, double* EVout) {
   const int tid = threadIdx.x;
   for (int e = tid; e < 32 * 32; e += NT) {
     const int u = e >> 5, v = e & 31;
@@ -1072,7 +1072,7 @@ __device__ inline void band_rotate(double* M, int ld, int n, int b0, int nb, con
 // tol / (2 relative gap)), and the tie rule is re-decided on its values.
 // Returns 1 when done, 0 on a barrier failure.
 template <typename T>
-__device__ __attribute__((noinline)) int refine_gate(const Slot& s, int k, bool ltr,
+__device__ __forceinline__ int refine_gate(const Slot& s, int k, bool ltr,
                                                      const double* Rptm, int Rr, int Cc,
                                                      int g, int G, Group& grp,
                                                      double* smem) {
@@ -1192,7 +1192,7 @@ __device__ __attribute__((noinline)) int refine_gate(const Slot& s, int k, bool 
 // iteration applies inside the kept span, so the move stays exact up to the
 // dropped numerical zeros.  Returns 1 when done, 0 on a barrier failure.
 template <typename T>
-__device__ __attribute__((noinline)) int refine_move(const Slot& s, int c, bool ltr, int Rr, int Cc, int g, int G,
+__device__ __forceinline__ int refine_move(const Slot& s, int c, bool ltr, int Rr, int Cc, int g, int G,
                            Group& grp, double* smem) {
   const int r = s.ctr[CT_RANK];
   double* A = s.R64;                                  // r x Cc

@@ -487,9 +487,10 @@ def test_eight_levels_one_launch_mixed_exact():
 def test_mixed_truncated_per_level():
     # Truncated mixed run at a cut with a small gap: the smallest relative cut
     # gaps of this circuit are 4.6e-6 (noise 1 x p) and 2.0e-5 (4 x p).  The
-    # Jacobi convergence threshold of the float32 rows (1e-7 relative,
-    # 1e-8 absolute) resolves the near-degenerate pairs at the cut, so each
-    # level meets the mixed tolerance against the float64 oracle.
+    # float64 band polish around the cut resolves the near-degenerate pairs
+    # the float32 Jacobi (default thresholds 3e-7 relative, 1e-9 absolute)
+    # leaves mixed there, so each level meets the mixed tolerance against
+    # the float64 oracle.
     n, chi = 10, 64
     layers = workloads.brickwork(n, 8, seed=21)
     obs = workloads.z_singles(n) + workloads.zz_neighbours(n)
