@@ -475,13 +475,18 @@ def main():
         return
 
     def timed(precision, steps, warmup):
-        for _ in range(warmup):
+        name = "fp64" if precision == nze.NZE_FP64 else "mixed"
+        for i in range(warmup):
             run_job(nze, w, layers, precision)
+            print(f"# {name} warmup job {i + 1}/{warmup} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = None
-        for _ in range(steps):
+        for i in range(steps):
             res = run_job(nze, w, layers, precision)
+            # run_job reads the results back, so the job has finished here
+            print(f"# {name} timed job {i + 1}/{steps} done at {time.perf_counter() - t0:.1f} s",
+                  file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         return dt, res
