@@ -276,17 +276,18 @@ def cpu_baseline(w, layers, timed_layer=5, budget_s=30.0, one_thread_updates=3):
                        f"with one thread in {dt1:.2f} s")}
 
 
-def serve_jobs(count, seed, workloads, nze):
+def serve_jobs(count, seed, workloads, nze, chis=(64, 128, 256)):
     """Synthetic job stream: n ~ U{16..64}, depth ~ U{10..30},
-    chi ~ U{64, 128, 256}, 4-8 levels evenly spaced in [1, 16] x 1e-3
-    (two-qubit depolarizing), Haar brickwork seeded per job, observables
-    <Z_(n/2)> and <X_1 X_2>.  Inputs (PTMs) are prepared before the clock."""
+    chi ~ U{64, 128, 256} (or U{chis}), 4-8 levels evenly spaced in
+    [1, 16] x 1e-3 (two-qubit depolarizing), Haar brickwork seeded per job,
+    observables <Z_(n/2)> and <X_1 X_2>.  Inputs (PTMs) are prepared before
+    the clock."""
     rng = np.random.default_rng(seed)
     jobs = []
     for i in range(count):
         n = int(rng.integers(16, 65))
         depth = int(rng.integers(10, 31))
-        chi = int(rng.choice([64, 128, 256]))
+        chi = int(rng.choice(list(chis)))
         L = int(rng.integers(4, 9))
         factors = list(np.linspace(1.0, 16.0, L))
         layers = workloads.brickwork(n, depth, seed=10000 * seed + i)
@@ -426,6 +427,8 @@ def main():
                     help="offered rate of the second serving leg; -1: 70 %% of "
                          "the completion rate measured in the first leg; 0: skip")
     ap.add_argument("--serve-sustainable-jobs", type=int, default=6)
+    ap.add_argument("--serve-chi", type=int, default=0,
+                    help="draw every serving job with this chi (0: the mix of 64, 128, 256)")
     ap.add_argument("--budget-s", type=float, default=570.0,
                     help="wall-time budget of the whole run: legs after the "
                          "timed steps are skipped (and say so) when their "
@@ -464,11 +467,12 @@ def main():
 
     if args.skip_main:
         out = {"metric": "reports", "n_gpus": 1, "data": "synthetic"}
+        chis = (args.serve_chi,) if args.serve_chi else (64, 128, 256)
         if args.serve:
-            jobs = serve_jobs(args.serve, 1, workloads, nze)
+            jobs = serve_jobs(args.serve, 1, workloads, nze, chis)
             out["serving"] = serve_run(nze, jobs, args.serve_rate, 1, nze.NZE_MIXED)
         if args.serve_sustainable_rate > 0:
-            jobs = jobs if args.serve else serve_jobs(200, 1, workloads, nze)
+            jobs = jobs if args.serve else serve_jobs(200, 1, workloads, nze, chis)
             out["serving_sustainable"] = serve_run(
                 nze, jobs, args.serve_sustainable_rate, 1, nze.NZE_MIXED)
         print(json.dumps(out), flush=True)
