@@ -148,6 +148,47 @@ __device__ inline void store2(double* p, double a, double b) {
   *(g_v2d*)p = x;
 }
 
+// Raw buffer resource over `bytes` bytes at `base` (gfx9 descriptor word 3).
+// A load at an offset outside [0, bytes) returns zeros and a store there is
+// dropped, so lanes whose row or column is out of range need no branch
+// around their accesses; with no branches the compiler counts the loads in
+// flight exactly and can wait for the older ones only.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr uint32_t OOB = 0x80000000u;   // an offset beyond every buffer here
+// base and bytes must be the same in every lane of the wave: they are read
+// from the first lane, so that the descriptor sits in scalar registers.
+__device__ inline rsrc_t make_rsrc(const void* base, size_t bytes) {
+  const uint64_t p = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+  const uint32_t n = __builtin_amdgcn_readfirstlane(
+      (uint32_t)(bytes < 0x7fffffffu ? bytes : 0x7fffffffu));
+  return __builtin_amdgcn_make_buffer_rsrc(
+      reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), (short)0, (int)n, 0x00020000);
+}
+__device__ inline void bload4(rsrc_t r, uint32_t off, float v[4]) {
+  const nze_v4f x = __builtin_bit_cast(nze_v4f, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+}
+__device__ inline void bload4(rsrc_t r, uint32_t off, double v[4]) {
+  const nze_v2d a = __builtin_bit_cast(nze_v2d, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  const nze_v2d b = __builtin_bit_cast(nze_v2d, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, 0));
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+
+typedef unsigned nze_v2u __attribute__((ext_vector_type(2)));
+typedef unsigned nze_v4u __attribute__((ext_vector_type(4)));
+__device__ inline void bstore2(rsrc_t r, uint32_t off, float a, float b) {
+  nze_v2f x;
+  x.x = a; x.y = b;
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(nze_v2u, x), r, off, 0, 0);
+}
+__device__ inline void bstore2(rsrc_t r, uint32_t off, double a, double b) {
+  nze_v2d x;
+  x.x = a; x.y = b;
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(nze_v4u, x), r, off, 0, 0);
+}
+
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;

@@ -219,26 +219,32 @@ __device__ inline PairLds pair_lds(double* smem) {
   return L;
 }
 
-// Gs = X_rows X_rows^T (32 x 32) in float64 from MFMA partials.
+// Gs = X_rows X_rows^T (32 x 32) in float64 from MFMA partials.  X holds R
+// rows of length C (leading dimension ld).  Each wave takes 64-column chunks
+// 256 apart; the loads of the next chunk are issued before the MFMAs of the
+// current one (branch-free buffer loads, zeros outside the rows and columns).
 template <typename T>
-__device__ __forceinline__ void pair_gram(const T* X, int ld, int C, const PairLds& L) {
+__device__ __forceinline__ void pair_gram(const T* X, int ld, int C, int R, const PairLds& L) {
   typedef typename AccT<T>::type acc_t;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
   const int r0 = L.rows[i], r1 = L.rows[16 + i];
+  const rsrc_t rs = make_rsrc(X, (size_t)R * ld * sizeof(T));
+  const uint32_t base0 = r0 >= 0 ? uint32_t(r0) * uint32_t(ld) * uint32_t(sizeof(T)) : OOB;
+  const uint32_t base1 = r1 >= 0 ? uint32_t(r1) * uint32_t(ld) * uint32_t(sizeof(T)) : OOB;
   // MFMA partial sums over 64 columns, accumulated in float64 across chunks
   double g00[4] = {0, 0, 0, 0}, g01[4] = {0, 0, 0, 0}, g11[4] = {0, 0, 0, 0};
-  for (int c0 = 16 * w; c0 < C; c0 += 256) {
-    T x0[4][4], x1[4][4];
+  T xa0[4][4], xa1[4][4], xb0[4][4], xb1[4][4];
+  auto fetch = [&](int c0, T (&x0)[4][4], T (&x1)[4][4]) {
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       const int c = c0 + 64 * h + 4 * kq;   // C is a multiple of 4
-      for (int s = 0; s < 4; ++s) { x0[h][s] = T(0); x1[h][s] = T(0); }
-      if (c < C) {
-        if (r0 >= 0) load4(X + (size_t)r0 * ld + c, x0[h]);
-        if (r1 >= 0) load4(X + (size_t)r1 * ld + c, x1[h]);
-      }
+      const uint32_t cb = uint32_t(c) * uint32_t(sizeof(T));
+      bload4(rs, (c < C && base0 != OOB) ? base0 + cb : OOB, x0[h]);
+      bload4(rs, (c < C && base1 != OOB) ? base1 + cb : OOB, x1[h]);
     }
+  };
+  auto accum = [&](const T (&x0)[4][4], const T (&x1)[4][4]) {
     acc_t a00 = {0, 0, 0, 0}, a01 = {0, 0, 0, 0}, a11 = {0, 0, 0, 0};
 #pragma unroll
     for (int h = 0; h < 4; ++h)
@@ -248,10 +254,52 @@ __device__ __forceinline__ void pair_gram(const T* X, int ld, int C, const PairL
         a01 = mfma4(x0[h][s], x1[h][s], a01);
         a11 = mfma4(x1[h][s], x1[h][s], a11);
       }
+#pragma unroll
     for (int r = 0; r < 4; ++r) {
       g00[r] += double(a00[r]);
       g01[r] += double(a01[r]);
       g11[r] += double(a11[r]);
+    }
+  };
+  int c0 = 16 * w;
+  if (C == 1024 || C == 2048) {
+    // the saturated shapes (chi 256 / 512): every wave takes exactly 4 / 8
+    // chunks, fully unrolled, so that the compiler waits for the loads of
+    // the chunk it multiplies only (in a loop it waits for all of them)
+    auto run = [&](auto nch) {
+      constexpr int NCH = decltype(nch)::value;
+      fetch(c0, xa0, xa1);
+#pragma unroll
+      for (int k = 0; k < NCH; ++k) {
+        if (k % 2 == 0) {
+          if (k + 1 < NCH) fetch(c0 + 256 * (k + 1), xb0, xb1);
+          __builtin_amdgcn_sched_barrier(0);
+          accum(xa0, xa1);
+        } else {
+          if (k + 1 < NCH) fetch(c0 + 256 * (k + 1), xa0, xa1);
+          __builtin_amdgcn_sched_barrier(0);
+          accum(xb0, xb1);
+        }
+      }
+    };
+    if (C == 1024) run(std::integral_constant<int, 4>());
+    else run(std::integral_constant<int, 8>());
+  } else if (c0 < C) {
+    // two register sets in turn: chunk k + 1 loads while chunk k multiplies
+    // (the scheduling barriers keep the compiler from sinking the loads of
+    // the next chunk down to their uses)
+    fetch(c0, xa0, xa1);
+    while (true) {
+      fetch(c0 + 256, xb0, xb1);
+      __builtin_amdgcn_sched_barrier(0);
+      accum(xa0, xa1);
+      c0 += 256;
+      if (c0 >= C) break;
+      fetch(c0 + 256, xa0, xa1);
+      __builtin_amdgcn_sched_barrier(0);
+      accum(xb0, xb1);
+      c0 += 256;
+      if (c0 >= C) break;
     }
   }
   double* P = L.Gp + w * 1024;
@@ -375,9 +423,10 @@ __device__ const double* inner_eigh(const PairLds& L, bool cross_only) {
   return Ga;   // the rotated Gram Q^T G Q
 }
 
-// rows <- Q^T rows for the pair's 32 rows of M (ld, ncols), in place.
+// rows <- Q^T rows for the pair's 32 rows of M (nrows rows, leading
+// dimension ld, ncols columns), in place.
 template <typename T, int VEC = 1>
-__device__ __forceinline__ void pair_rotate(T* M, int ld, int ncols, const PairLds& L) {
+__device__ __forceinline__ void pair_rotate(T* M, int ld, int ncols, int nrows, const PairLds& L) {
   typedef typename AccT<T>::type acc_t;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
@@ -391,17 +440,30 @@ __device__ __forceinline__ void pair_rotate(T* M, int ld, int ncols, const PairL
   if (VEC && (ld & 3) == 0 && (ncols & 3) == 0 && (reinterpret_cast<uintptr_t>(M) & 15) == 0) {
     // vector path: lane (i, kq) loads four consecutive columns c0 + 4i .. +3
     // of row 4s + kq; MFMA j takes column c0 + 4i + j, and each output row's
-    // four columns leave as one vector store
-    for (int c0 = 64 * w; c0 < ncols; c0 += 256) {
+    // four columns leave as one vector store.  Branch-free buffer accesses
+    // (rows past the pair and columns past the end read zeros and drop
+    // their stores); the loads of the next 64-column chunk are issued
+    // before the MFMAs of the current one.
+    const rsrc_t rs = make_rsrc(M, (size_t)nrows * ld * sizeof(T));
+    const uint32_t rowb = uint32_t(ld) * uint32_t(sizeof(T));
+    uint32_t sb[8], db0[4], db1[4];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) sb[s] = src[s] >= 0 ? uint32_t(src[s]) * rowb : OOB;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      db0[r] = dst0[r] >= 0 ? uint32_t(dst0[r]) * rowb : OOB;
+      db1[r] = dst1[r] >= 0 ? uint32_t(dst1[r]) * rowb : OOB;
+    }
+    T xa[8][4], xb[8][4];
+    auto fetch = [&](int c0, T (&x)[8][4]) {
+      const int c = c0 + 4 * i;
+      const uint32_t cb = uint32_t(c) * uint32_t(sizeof(T));
+#pragma unroll
+      for (int s = 0; s < 8; ++s) bload4(rs, (c < ncols && sb[s] != OOB) ? sb[s] + cb : OOB, x[s]);
+    };
+    auto rotate = [&](int c0, const T (&x)[8][4]) {
       const int c = c0 + 4 * i;
       const bool cok = c < ncols;
-      T x[8][4];
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) x[s][j] = T(0);
-        if (cok && src[s] >= 0) load4(M + (size_t)src[s] * ld + c, x[s]);
-      }
       // two column pairs at a time (fewer live accumulators)
 #pragma unroll
       for (int jh = 0; jh < 4; jh += 2) {
@@ -413,13 +475,55 @@ __device__ __forceinline__ void pair_rotate(T* M, int ld, int ncols, const PairL
           d1a = mfma4(qa[1][s], x[s][jh], d1a);
           d1b = mfma4(qa[1][s], x[s][jh + 1], d1b);
         }
-        if (cok) {
+        const uint32_t cb = uint32_t(c + jh) * uint32_t(sizeof(T));
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            if (dst0[r] >= 0) store2(M + (size_t)dst0[r] * ld + c + jh, d0a[r], d0b[r]);
-            if (dst1[r] >= 0) store2(M + (size_t)dst1[r] * ld + c + jh, d1a[r], d1b[r]);
+        for (int r = 0; r < 4; ++r) {
+          bstore2(rs, (cok && db0[r] != OOB) ? db0[r] + cb : OOB, T(d0a[r]), T(d0b[r]));
+          bstore2(rs, (cok && db1[r] != OOB) ? db1[r] + cb : OOB, T(d1a[r]), T(d1b[r]));
+        }
+      }
+    };
+    int c0 = 64 * w;
+    if constexpr (sizeof(T) == 8) {
+      // float64 rows: one register set (two do not fit without spilling)
+      for (; c0 < ncols; c0 += 256) {
+        fetch(c0, xa);
+        rotate(c0, xa);
+      }
+    } else if (ncols == 1024 || ncols == 2048) {
+      // the saturated shapes: every wave takes exactly 4 / 8 chunks, fully
+      // unrolled so that the compiler waits for the current chunk only
+      auto run = [&](auto nch) {
+        constexpr int NCH = decltype(nch)::value;
+        fetch(c0, xa);
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+          if (k % 2 == 0) {
+            if (k + 1 < NCH) fetch(c0 + 256 * (k + 1), xb);
+            __builtin_amdgcn_sched_barrier(0);
+            rotate(c0 + 256 * k, xa);
+          } else {
+            if (k + 1 < NCH) fetch(c0 + 256 * (k + 1), xa);
+            __builtin_amdgcn_sched_barrier(0);
+            rotate(c0 + 256 * k, xb);
           }
         }
+      };
+      if (ncols == 1024) run(std::integral_constant<int, 4>());
+      else run(std::integral_constant<int, 8>());
+    } else if (c0 < ncols) {
+      fetch(c0, xa);
+      while (true) {
+        fetch(c0 + 256, xb);
+        __builtin_amdgcn_sched_barrier(0);
+        rotate(c0, xa);
+        c0 += 256;
+        if (c0 >= ncols) break;
+        fetch(c0 + 256, xa);
+        __builtin_amdgcn_sched_barrier(0);
+        rotate(c0, xb);
+        c0 += 256;
+        if (c0 >= ncols) break;
       }
     }
     return;
@@ -455,25 +559,32 @@ __device__ __forceinline__ void pair_rotate(T* M, int ld, int ncols, const PairL
   }
 }
 
+// Global row of pair row tid (< 32) of the visit of blocks I, J: rows are
+// numbered in the sweep's order (fixed for the sweep), -1 past the end.
+__device__ inline int pair_row(const int* order, int I, int J, int nb, int R) {
+  const int tid = threadIdx.x;
+  if (tid >= 32) return -1;
+  const int blk = tid < 16 ? I : J;
+  const int r = blk * BW + (tid & 15);
+  return (blk < nb && r < R) ? load1(order + r) : -1;
+}
+
 // One pair step of sweep `sw`: Gram, convergence test, inner solve, rotate.
+// prow: pair_row of this thread, loaded before the wait for the blocks.
 template <typename T, int VEC = 1>
 __device__ __forceinline__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
                             int J, int nb, int sw, double F2, double* smem,
-                            bool timed, const int* order, Group& grp,
+                            bool timed, Group& grp,
                             int* verX, int* verW, int target, bool last_round,
-                            bool cross_only, bool forced) {
+                            bool cross_only, bool forced, int prow) {
   const PairLds L = pair_lds(smem);
   const int tid = threadIdx.x;
   PhaseClock clk(timed && s.prof != nullptr);
   __syncthreads();
-  if (tid < 32) {
-    const int blk = tid < 16 ? I : J;
-    const int r = blk * BW + (tid & 15);
-    L.rows[tid] = (blk < nb && r < R) ? load1(order + r) : -1;
-  }
+  if (tid < 32) L.rows[tid] = prow;
   if (tid == 0) L.flag[1] = 0;
   __syncthreads();
-  pair_gram<T>(X, C, C, L);
+  pair_gram<T>(X, C, C, R, L);
   clk.lap(s.prof, PF_GRAM);
   int go = 1;
   if (!forced) {
@@ -508,7 +619,7 @@ __device__ __forceinline__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, in
     Gfin = inner_eigh(L, cross_only);
     clk.lap(s.prof, PF_EIGH);
     if (clk.on && tid == 0) s.prof[PF_PAIRS] += 1.0;
-    pair_rotate<T, VEC>(X, C, C, L);
+    pair_rotate<T, VEC>(X, C, C, R, L);
     clk.lap(s.prof, PF_ROTX);
   }
   // the last round visits every block once: the diagonal of the pair's Gram
@@ -519,7 +630,7 @@ __device__ __forceinline__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, in
   if (s.no_acc) return true;
   // accumulator rows: previous visits of both blocks first, in visit order
   if (!blocks_wait(grp, verW, I, J, target)) return false;
-  if (go) pair_rotate<T, VEC>(W, R, R, L);
+  if (go) pair_rotate<T, VEC>(W, R, R, R, L);
   blocks_release(grp, verW, I, J);
   clk.lap(s.prof, PF_ROTW);
   return true;
@@ -645,6 +756,8 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
       {
         const int I = tourney_block(q, t, nbe);
         const int J = tourney_block(nbe - 1 - q, t, nbe);
+        // the row order is fixed for the sweep: its load overlaps the wait
+        const int prow = pair_row(s.perm, I, J, nb, R);
         PhaseClock wclk(s.prof != nullptr);
         if (!blocks_wait(grp, ver, I, J, base + t)) return false;
         if (wclk.on) {
@@ -654,8 +767,8 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
             atomicAdd(&s.prof[PF_WAIT_ALL], double(now - wclk.t) / G);
           }
         }
-        if (!jacobi_pair<T, VEC>(s, X, W, R, C, I, J, nb, sw, F2, smem, g == 0, s.perm,
-                            grp, ver, wver, base + t, t == rounds - 1, cross_only, forced))
+        if (!jacobi_pair<T, VEC>(s, X, W, R, C, I, J, nb, sw, F2, smem, g == 0, grp, ver, wver, base + t, t == rounds - 1, cross_only, forced,
+                            prow))
           return false;
       }
     }
