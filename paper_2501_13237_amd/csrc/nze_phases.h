@@ -394,19 +394,22 @@ __device__ const double* inner_eigh(const PairLds& L, bool cross_only) {
   __syncthreads();
   const int nsteps = cross_only ? 16 : 31;
   const int u0 = 2 * P;
+  // lane l of a wave computes the rotation of pair l & 15 (its column pair
+  // P2); the rotation of its row pair P = 4 w + l / 16 comes from lane P of
+  // the same wave, which computed it as its own column pair
+  const int srcP = P & 15;
   for (int st = 0; st < nsteps; ++st) {
     int p, q, p2, q2;
     sweep_pair32(P, st, p, q);
     sweep_pair32(P2, st, p2, q2);
-    const double app = Ga[p * GLD + p], aqq = Ga[q * GLD + q], apq = Ga[p * GLD + q];
     const double bpp = Ga[p2 * GLD + p2], bqq = Ga[q2 * GLD + q2], bpq = Ga[p2 * GLD + q2];
     const double g11 = Ga[p * GLD + p2], g12 = Ga[p * GLD + q2];
     const double g21 = Ga[q * GLD + p2], g22 = Ga[q * GLD + q2];
     const double qa = L.Qs[u0 * GLD + p2], qb = L.Qs[u0 * GLD + q2];
     const double qc = L.Qs[(u0 + 1) * GLD + p2], qd = L.Qs[(u0 + 1) * GLD + q2];
-    double c, sn, c2, s2;
-    jacobi_cs(app, aqq, apq, floor_abs, c, sn);
+    double c2, s2;
     jacobi_cs(bpp, bqq, bpq, floor_abs, c2, s2);
+    const double c = __shfl(c2, srcP, 64), sn = __shfl(s2, srcP, 64);
     const double h11 = c * g11 - sn * g21, h12 = c * g12 - sn * g22;
     const double h21 = sn * g11 + c * g21, h22 = sn * g12 + c * g22;
     Gb[p * GLD + p2] = c2 * h11 - s2 * h12;
