@@ -223,7 +223,9 @@ __device__ inline PairLds pair_lds(double* smem) {
 // rows of length C (leading dimension ld).  Each wave takes 64-column chunks
 // 256 apart; the loads of the next chunk are issued before the MFMAs of the
 // current one (branch-free buffer loads, zeros outside the rows and columns).
-template <typename T>
+// VEC = 0 (the kernel built for two workgroups per CU, which hides latency
+// with the other workgroup and has half the registers): one register set.
+template <typename T, int VEC = 1>
 __device__ __forceinline__ void pair_gram(const T* X, int ld, int C, int R, const PairLds& L) {
   typedef typename AccT<T>::type acc_t;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -262,7 +264,12 @@ __device__ __forceinline__ void pair_gram(const T* X, int ld, int C, int R, cons
     }
   };
   int c0 = 16 * w;
-  if (C == 1024 || C == 2048) {
+  if constexpr (VEC == 0) {
+    for (; c0 < C; c0 += 256) {
+      fetch(c0, xa0, xa1);
+      accum(xa0, xa1);
+    }
+  } else if (C == 1024 || C == 2048) {
     // the saturated shapes (chi 256 / 512): every wave takes exactly 4 / 8
     // chunks, fully unrolled, so that the compiler waits for the loads of
     // the chunk it multiplies only (in a loop it waits for all of them)
@@ -398,10 +405,7 @@ __device__ const double* inner_eigh(const PairLds& L, bool cross_only) {
   // P2); the rotation of its row pair P = 4 w + l / 16 comes from lane P of
   // the same wave, which computed it as its own column pair
   const int srcP = P & 15;
-  for (int st = 0; st < nsteps; ++st) {
-    int p, q, p2, q2;
-    sweep_pair32(P, st, p, q);
-    sweep_pair32(P2, st, p2, q2);
+  auto step = [&](int p, int q, int p2, int q2) {
     const double bpp = Ga[p2 * GLD + p2], bqq = Ga[q2 * GLD + q2], bpq = Ga[p2 * GLD + q2];
     const double g11 = Ga[p * GLD + p2], g12 = Ga[p * GLD + q2];
     const double g21 = Ga[q * GLD + p2], g22 = Ga[q * GLD + q2];
@@ -422,6 +426,22 @@ __device__ const double* inner_eigh(const PairLds& L, bool cross_only) {
     L.Qs[(u0 + 1) * GLD + q2] = s2 * qc + c2 * qd;
     double* t = Ga; Ga = Gb; Gb = t;
     __syncthreads();
+  };
+  // the pairing of sweep_pair32, stepped incrementally: cross-block steps
+  for (int st = 0; st < 16; ++st)
+    step(P, 16 + ((P + st) & 15), P2, 16 + ((P2 + st) & 15));
+  if (nsteps > 16) {
+    // tournament inside each block: position j of pair k (base 0 or 16)
+    // meets (j - 1 + r) mod 15 and (14 - j + r) mod 15, r = st - 16
+    const int bP = P < 8 ? 0 : 16, jP = P & 7, bQ = P2 < 8 ? 0 : 16, jQ = P2 & 7;
+    int aP = jP == 0 ? 0 : jP - 1, cP = 14 - jP, aQ = jQ == 0 ? 0 : jQ - 1, cQ = 14 - jQ;
+    for (int r = 0; r < 15; ++r) {
+      step(bP + (jP == 0 ? 0 : 1 + aP), bP + 1 + cP, bQ + (jQ == 0 ? 0 : 1 + aQ), bQ + 1 + cQ);
+      aP = aP == 14 ? 0 : aP + 1;
+      cP = cP == 14 ? 0 : cP + 1;
+      aQ = aQ == 14 ? 0 : aQ + 1;
+      cQ = cQ == 14 ? 0 : cQ + 1;
+    }
   }
   return Ga;   // the rotated Gram Q^T G Q
 }
@@ -587,7 +607,7 @@ __device__ __forceinline__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, in
   if (tid < 32) L.rows[tid] = prow;
   if (tid == 0) L.flag[1] = 0;
   __syncthreads();
-  pair_gram<T>(X, C, C, R, L);
+  pair_gram<T, VEC>(X, C, C, R, L);
   clk.lap(s.prof, PF_GRAM);
   int go = 1;
   if (!forced) {
