@@ -357,53 +357,23 @@ __device__ inline void jacobi_cs(double gpp, double gqq, double gpq,
   sn = ra ? xa * ca : 0.0;
 }
 
-// Pairing of the 32 rows of a block pair (rows 0-15: block I, 16-31: block
-// J) in one cyclic sweep of 31 steps of 16 disjoint rotations, cross-block
-// pairs first: steps 0-15 pair row k of I with row 16 + (k + st) mod 16 of J
-// (all 256 cross pairs); steps 16-30 are a round-robin tournament inside each
-// block (pairs 0-7 in I, 8-15 in J; all 2 x 120 intra pairs).
-__device__ inline void sweep_pair32(int k, int st, int& p, int& q) {
-  if (st < 16) {
-    p = k;
-    q = 16 + ((k + st) & 15);
-    return;
-  }
-  const int r = st - 16, base = k < 8 ? 0 : 16, j = k & 7;
-  p = base + (j == 0 ? 0 : 1 + ((j - 1 + r) % 15));
-  q = base + 1 + ((14 - j + r) % 15);
-}
-
-// One cyclic parallel Jacobi sweep on the 32x32 symmetric Gs (float64, LDS),
-// cross-block steps first (both blocks enter with nearly orthogonal rows
-// once a sweep has visited them, so the cross entries carry most of the
-// off-diagonal weight); Qs accumulates the rotations.  Thread t owns the 2x2
-// block (pair t/16, pair t%16) of G and rows 2(t/16), 2(t/16)+1 of Qs at pair
-// t%16, and computes the two rotations it needs itself from the step's
-// pivots: every LDS read of a step is issued at once, with no second round
-// trip to share the rotations, and the two rotation chains run side by side.
-// Threads that need the same rotation compute it from the same values with
-// the same instructions, so they agree bit for bit.  G ping-pongs between Gs
-// and a second buffer (the dead Gram partials): one workgroup barrier a
-// step.  With cross_only the sweep stops after the 16 cross-block steps.
-// Returns the buffer that holds the rotated Gram Q^T G Q.
-__device__ const double* inner_eigh(const PairLds& L, bool cross_only) {
+// One cyclic parallel Jacobi sweep on the 32x32 symmetric Gram in Ga
+// (float64, LDS), cross-block steps first (both blocks enter with nearly
+// orthogonal rows once a sweep has visited them, so the cross entries carry
+// most of the off-diagonal weight); Qs accumulates the rotations.  Thread t
+// owns the 2x2 block (pair t/16, pair t%16) of G and rows 2(t/16),
+// 2(t/16)+1 of Qs at pair t%16.  Lane l of a wave computes the rotation of
+// pair l & 15 (its column pair) from the step's pivots; the rotation of its
+// row pair P = t/16 = 4 w + l/16 comes from lane P of the same wave, which
+// computed it as its own column pair from the same values with the same
+// instructions.  G ping-pongs between Ga and Gb (swapped on return, Ga holds
+// the result): one workgroup barrier a step.  With cross_only the sweep
+// stops after the 16 cross-block steps.  Pivots with |g_pq| <= floor_abs are
+// not rotated.
+__device__ __forceinline__ void gram_sweep32(const PairLds& L, double*& Ga, double*& Gb,
+                                             double floor_abs, bool cross_only) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < 32 * 32; e += NT) {
-    const int u = e >> 5, v = e & 31;
-    L.Qs[u * GLD + v] = (u == v) ? 1.0 : 0.0;
-  }
-  double dmax = 0.0;
-  for (int u = 0; u < 32; ++u) dmax = fmax(dmax, L.Gs[u * GLD + u]);
-  const double floor_abs = 1e-30 * dmax;
-  const int P = tid >> 4, P2 = tid & 15;
-  double* Ga = L.Gs;
-  double* Gb = L.Gp;          // 32 x GLD, free once the Gram is reduced
-  __syncthreads();
-  const int nsteps = cross_only ? 16 : 31;
-  const int u0 = 2 * P;
-  // lane l of a wave computes the rotation of pair l & 15 (its column pair
-  // P2); the rotation of its row pair P = 4 w + l / 16 comes from lane P of
-  // the same wave, which computed it as its own column pair
+  const int P = tid >> 4, P2 = tid & 15, u0 = 2 * P;
   const int srcP = P & 15;
   auto step = [&](int p, int q, int p2, int q2) {
     const double bpp = Ga[p2 * GLD + p2], bqq = Ga[q2 * GLD + q2], bpq = Ga[p2 * GLD + q2];
@@ -427,12 +397,17 @@ __device__ const double* inner_eigh(const PairLds& L, bool cross_only) {
     double* t = Ga; Ga = Gb; Gb = t;
     __syncthreads();
   };
-  // the pairing of sweep_pair32, stepped incrementally: cross-block steps
+  // pairing of the 32 rows (rows 0-15: block I, 16-31: block J), 16
+  // disjoint rotations a step: steps 0-15 pair row k of I with row
+  // 16 + (k + st) mod 16 of J (all 256 cross pairs) ...
   for (int st = 0; st < 16; ++st)
     step(P, 16 + ((P + st) & 15), P2, 16 + ((P2 + st) & 15));
-  if (nsteps > 16) {
-    // tournament inside each block: position j of pair k (base 0 or 16)
-    // meets (j - 1 + r) mod 15 and (14 - j + r) mod 15, r = st - 16
+  if (!cross_only) {
+    // ... steps 16-30 a round-robin tournament inside each block (pairs
+    // 0-7 in I, 8-15 in J; all 2 x 120 intra pairs): pair k = base + j
+    // (base 0 or 16) takes rows base + (j == 0 ? 0 : 1 + (j - 1 + r) mod 15)
+    // and base + 1 + (14 - j + r) mod 15 at r = st - 16, stepped here
+    // incrementally
     const int bP = P < 8 ? 0 : 16, jP = P & 7, bQ = P2 < 8 ? 0 : 16, jQ = P2 & 7;
     int aP = jP == 0 ? 0 : jP - 1, cP = 14 - jP, aQ = jQ == 0 ? 0 : jQ - 1, cQ = 14 - jQ;
     for (int r = 0; r < 15; ++r) {
@@ -443,6 +418,23 @@ __device__ const double* inner_eigh(const PairLds& L, bool cross_only) {
       cQ = cQ == 14 ? 0 : cQ + 1;
     }
   }
+}
+
+// The pair solve: one sweep of gram_sweep32 on the pair's Gram in Gs, from
+// Qs = I.  Returns the buffer that holds the rotated Gram Q^T G Q.
+__device__ const double* inner_eigh(const PairLds& L, bool cross_only) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 32 * 32; e += NT) {
+    const int u = e >> 5, v = e & 31;
+    L.Qs[u * GLD + v] = (u == v) ? 1.0 : 0.0;
+  }
+  double dmax = 0.0;
+  for (int u = 0; u < 32; ++u) dmax = fmax(dmax, L.Gs[u * GLD + u]);
+  const double floor_abs = 1e-30 * dmax;
+  double* Ga = L.Gs;
+  double* Gb = L.Gp;          // 32 x GLD, free once the Gram is reduced
+  __syncthreads();
+  gram_sweep32(L, Ga, Gb, floor_abs, cross_only);
   return Ga;   // the rotated Gram Q^T G Q
 }
 
@@ -1110,7 +1102,6 @@ __device__ __forceinline__ void band_eigh(const PairLds& L, int nb, double* Vout
   __syncthreads();
   double* Ga = L.Gs;
   double* Gb = L.Gp;
-  const int P = tid >> 4, P2 = tid & 15, u0 = 2 * P;
   double* red = L.Gp + 2048;
   for (int sweep = 0; sweep < 12; ++sweep) {
     // convergence on the entries of the current Gram
@@ -1129,32 +1120,7 @@ __device__ __forceinline__ void band_eigh(const PairLds& L, int nb, double* Vout
     worst = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     __syncthreads();
     if (worst <= 1e-15) break;
-    for (int st = 0; st < 31; ++st) {
-      int p, q, p2, q2;
-      sweep_pair32(P, st, p, q);
-      sweep_pair32(P2, st, p2, q2);
-      const double app = Ga[p * GLD + p], aqq = Ga[q * GLD + q], apq = Ga[p * GLD + q];
-      const double bpp = Ga[p2 * GLD + p2], bqq = Ga[q2 * GLD + q2], bpq = Ga[p2 * GLD + q2];
-      const double g11 = Ga[p * GLD + p2], g12 = Ga[p * GLD + q2];
-      const double g21 = Ga[q * GLD + p2], g22 = Ga[q * GLD + q2];
-      const double qa = L.Qs[u0 * GLD + p2], qb = L.Qs[u0 * GLD + q2];
-      const double qc = L.Qs[(u0 + 1) * GLD + p2], qd = L.Qs[(u0 + 1) * GLD + q2];
-      double c, sn, c2, s2;
-      jacobi_cs(app, aqq, apq, 0.0, c, sn);
-      jacobi_cs(bpp, bqq, bpq, 0.0, c2, s2);
-      const double h11 = c * g11 - sn * g21, h12 = c * g12 - sn * g22;
-      const double h21 = sn * g11 + c * g21, h22 = sn * g12 + c * g22;
-      Gb[p * GLD + p2] = c2 * h11 - s2 * h12;
-      Gb[p * GLD + q2] = s2 * h11 + c2 * h12;
-      Gb[q * GLD + p2] = c2 * h21 - s2 * h22;
-      Gb[q * GLD + q2] = s2 * h21 + c2 * h22;
-      L.Qs[u0 * GLD + p2] = c2 * qa - s2 * qb;
-      L.Qs[u0 * GLD + q2] = s2 * qa + c2 * qb;
-      L.Qs[(u0 + 1) * GLD + p2] = c2 * qc - s2 * qd;
-      L.Qs[(u0 + 1) * GLD + q2] = s2 * qc + c2 * qd;
-      double* t = Ga; Ga = Gb; Gb = t;
-      __syncthreads();
-    }
+    gram_sweep32(L, Ga, Gb, 0.0, false);
   }
   // columns in decreasing eigenvalue order (selection by rank; ties by index)
   if (tid < 32) {
