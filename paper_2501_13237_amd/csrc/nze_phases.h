@@ -370,9 +370,17 @@ __device__ inline void jacobi_cs(double gpp, double gqq, double gpq,
 // the result): one workgroup barrier a step.  With cross_only the sweep
 // stops after the 16 cross-block steps.  Pivots with |g_pq| <= floor_abs are
 // not rotated.
+// skip_tol > 0: after the cross-block steps, the intra-block steps run only
+// if some intra-block entry fails the visit's convergence test
+// (|g_uv| > skip_tol (sqrt(g_uu g_vv) + ratio_abs sqrt(F2 max(g_uu, g_vv))));
+// entries that pass it are left to later visits, and the sweeps still end
+// only when every pair of every visit passes the test.
 __device__ __forceinline__ void gram_sweep32(const PairLds& L, double*& Ga, double*& Gb,
-                                             double floor_abs, bool cross_only) {
+                                             double floor_abs, bool cross_only,
+                                             double skip_tol = 0.0, double ratio_abs = 0.0,
+                                             double F2 = 0.0) {
   const int tid = threadIdx.x;
+  if (tid == 0) L.flag[0] = 0;   // ordered by the barrier of the first step
   const int P = tid >> 4, P2 = tid & 15, u0 = 2 * P;
   const int srcP = P & 15;
   auto step = [&](int p, int q, int p2, int q2) {
@@ -402,7 +410,29 @@ __device__ __forceinline__ void gram_sweep32(const PairLds& L, double*& Ga, doub
   // 16 + (k + st) mod 16 of J (all 256 cross pairs) ...
   for (int st = 0; st < 16; ++st)
     step(P, 16 + ((P + st) & 15), P2, 16 + ((P2 + st) & 15));
-  if (!cross_only) {
+  if (cross_only) return;
+  if (skip_tol > 0.0) {
+    // thread t: entry (t / 16, t % 16) of each block's 16 x 16 corner
+    const int u = tid >> 4, v = tid & 15;
+    float worst = 0.f;
+    if (v > u) {
+      for (int b = 0; b < 32; b += 16) {
+        const double guu = Ga[(b + u) * GLD + b + u], gvv = Ga[(b + v) * GLD + b + v];
+        const double guv = fabs(Ga[(b + u) * GLD + b + v]);
+        const double den = __builtin_amdgcn_sqrt(guu * gvv) +
+                           ratio_abs * __builtin_amdgcn_sqrt(F2 * fmax(guu, gvv));
+        const double q = den > 0.0 ? guv * __builtin_amdgcn_rcp(den) : (guv > 0.0 ? 1.0 : 0.0);
+        worst = fmaxf(worst, (q == q) ? float(q) : 1.0f);
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) worst = fmaxf(worst, __shfl_xor(worst, o, 64));
+    if ((tid & 63) == 0 && worst > float(skip_tol)) L.flag[0] = 1;
+    __syncthreads();
+    const int need = L.flag[0];
+    __syncthreads();
+    if (!need) return;
+  }
+  {
     // ... steps 16-30 a round-robin tournament inside each block (pairs
     // 0-7 in I, 8-15 in J; all 2 x 120 intra pairs): pair k = base + j
     // (base 0 or 16) takes rows base + (j == 0 ? 0 : 1 + (j - 1 + r) mod 15)
@@ -421,8 +451,11 @@ __device__ __forceinline__ void gram_sweep32(const PairLds& L, double*& Ga, doub
 }
 
 // The pair solve: one sweep of gram_sweep32 on the pair's Gram in Gs, from
-// Qs = I.  Returns the buffer that holds the rotated Gram Q^T G Q.
-__device__ const double* inner_eigh(const PairLds& L, bool cross_only) {
+// Qs = I, its intra-block steps skipped when those entries already pass the
+// visit's convergence test (skip_tol = the test's threshold).  Returns the
+// buffer that holds the rotated Gram Q^T G Q.
+__device__ const double* inner_eigh(const PairLds& L, bool cross_only, double skip_tol,
+                                   double ratio_abs, double F2) {
   const int tid = threadIdx.x;
   for (int e = tid; e < 32 * 32; e += NT) {
     const int u = e >> 5, v = e & 31;
@@ -434,7 +467,7 @@ __device__ const double* inner_eigh(const PairLds& L, bool cross_only) {
   double* Ga = L.Gs;
   double* Gb = L.Gp;          // 32 x GLD, free once the Gram is reduced
   __syncthreads();
-  gram_sweep32(L, Ga, Gb, floor_abs, cross_only);
+  gram_sweep32(L, Ga, Gb, floor_abs, cross_only, skip_tol, ratio_abs, F2);
   return Ga;   // the rotated Gram Q^T G Q
 }
 
@@ -602,10 +635,10 @@ __device__ __forceinline__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, in
   pair_gram<T, VEC>(X, C, C, R, L);
   clk.lap(s.prof, PF_GRAM);
   int go = 1;
+  const double tol = jacobi_threshold<T>(s, C);
+  const double ratio_abs = s.tol_abs / tol;
   if (!forced) {
     // convergence test: |g_uv| > tol sqrt(g_uu g_vv) + tol_abs sqrt(F2 max)
-    const double tol = jacobi_threshold<T>(s, C);
-    const double ratio_abs = s.tol_abs / tol;
     float worst = 0.f;   // largest |g_uv| / (sqrt(g_uu g_vv) + ratio_abs sqrt(F2 max))
     for (int e = tid; e < 1024; e += NT) {
       const int u = e >> 5, v = e & 31;
@@ -631,7 +664,7 @@ __device__ __forceinline__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, in
   const double* Gfin = L.Gs;
   if (go) {
     if (tid == 0) atomicAdd(&s.ctr[CT_ROT + sw], 1);
-    Gfin = inner_eigh(L, cross_only);
+    Gfin = inner_eigh(L, cross_only, tol, ratio_abs, F2);
     clk.lap(s.prof, PF_EIGH);
     if (clk.on && tid == 0) s.prof[PF_PAIRS] += 1.0;
     pair_rotate<T, VEC>(X, C, C, R, L);
