@@ -120,11 +120,12 @@ __device__ __forceinline__ void set_identity(T* W, int n, int g, int G) {
 
 // ------------------------------------------------------------ theta phase
 
-// X <- (R x 1)(M_k M_{k+1}); also W = I and F2 = ||X||^2.
+// X <- (R x 1)(M_k M_{k+1}); also W = I (init_w), or a second copy of the
+// block in X2 (the float64 refinement's unrotated block).
 template <typename T>
 __device__ __forceinline__ void phase_theta(const Slot& s, int k, bool ltr, const double* R,
                             int g, int G, double* smem, bool count = true,
-                            bool init_w = true) {
+                            bool init_w = true, T* X2 = nullptr) {
   typedef typename AccT<T>::type acc_t;
   const int cl = s.dims[k], cm = s.dims[k + 1], cr = s.dims[k + 2];
   const T* A = site_ptr<T>(s, k);          // (4 cl) x cm
@@ -172,8 +173,10 @@ __device__ __forceinline__ void phase_theta(const Slot& s, int k, bool ltr, cons
           const int P = 4 * p2 + q2;
           T o = T(0);
           for (int Q = 0; Q < 16; ++Q) o += T(Rs[P * 16 + Q]) * th[Q];
-          if (ltr) X[(size_t)(a * 4 + p2) * ldx + q2 * cr + b] = o;
-          else X[(size_t)(q2 * cr + b) * ldx + a * 4 + p2] = o;
+          const size_t e = ltr ? (size_t)(a * 4 + p2) * ldx + q2 * cr + b
+                               : (size_t)(q2 * cr + b) * ldx + a * 4 + p2;
+          X[e] = o;
+          if (X2) X2[e] = o;
         }
     }
   }
@@ -1201,16 +1204,15 @@ __device__ inline void band_rotate(double* M, int ld, int n, int b0, int nb, con
 // of Theta' (indexed (a, p')), whose rotated rows are s_i v_i^T.  The kept
 // rows divided by their norms, orthonormalised in float64 (ns_rows), give
 // Q = U_r^T (resp. V_r^T); the other factor is the float64 projection of the
-// recomputed block, Y = Q X0^T.  A float64 Rayleigh-Ritz polish of the BAND
+// unrotated block X0 (the copy the contraction left in W), Y = Q X0^T.  A
+// float64 Rayleigh-Ritz polish of the BAND
 // kept and BAND dropped directions around a chi cut resolves the mixing the
 // float32 Jacobi leaves between near-degenerate directions there (about
 // tol / (2 relative gap)), and the tie rule is re-decided on its values.
 // Returns 1 when done, 0 on a barrier failure.
 template <typename T>
-__device__ __forceinline__ int refine_gate(const Slot& s, int k, bool ltr,
-                                                     const double* Rptm, int Rr, int Cc,
-                                                     int g, int G, Group& grp,
-                                                     double* smem) {
+__device__ __forceinline__ int refine_gate(const Slot& s, int k, bool ltr, int Rr, int Cc,
+                                           int g, int G, Group& grp, double* smem) {
   const int r = s.ctr[CT_RANK];
   // the band: only at a cut set by chi, and only over dropped directions
   // within three decades of the last kept one
@@ -1238,11 +1240,10 @@ __device__ __forceinline__ int refine_gate(const Slot& s, int k, bool ltr,
   double* Q = ns_rows(A, C, Cc, rr, B, s, g, G, grp);
   if (!Q) return 0;
   double* Y = Q == A ? C : A;
-  // the block again, in the Jacobi's orientation (its sites are untouched
-  // until the gathers below)
-  phase_theta<T>(s, k, !ltr, Rptm, g, G, smem, false, false);
-  if (!group_sync(grp)) return 0;
-  gemm64<double, T, true>(Q, Cc, X, Cc, Y, Rr, rr, Rr, Cc, g, G);   // Y = Q X0^T
+  // the unrotated block X0, in the Jacobi's orientation: the copy that the
+  // contraction left in W
+  const T* X0 = reinterpret_cast<const T*>(s.W);
+  gemm64<double, T, true>(Q, Cc, X0, Cc, Y, Rr, rr, Rr, Cc, g, G);   // Y = Q X0^T
   if (!group_sync(grp)) return 0;
   const int nb = lo + hi, b0 = r - lo;
   if (hi > 0 && lo > 0) {
@@ -1391,7 +1392,9 @@ __device__ __forceinline__ bool op_gate(const Slot& s, int k, bool ltr, const do
   T* X = reinterpret_cast<T*>(s.X);
   T* W = reinterpret_cast<T*>(s.W);
   PhaseClock clk(g == 0 && s.prof != nullptr);
-  phase_theta<T>(s, k, rows_ap, R, g, G, smem, true, !s.no_acc);
+  // (the refinement keeps a copy of the unrotated block in W, which the
+  // Jacobi without accumulator leaves free)
+  phase_theta<T>(s, k, rows_ap, R, g, G, smem, true, !s.no_acc, refine ? W : nullptr);
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_THETA);
   if (!phase_jacobi<T, VEC>(s, X, W, Rr, Cc, g, G, grp, smem)) return false;
@@ -1403,7 +1406,7 @@ __device__ __forceinline__ bool op_gate(const Slot& s, int k, bool ltr, const do
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_SELECT);
   if constexpr (sizeof(T) == 4) if (refine) {
-    if (!refine_gate<T>(s, k, ltr, R, Rr, Cc, g, G, grp, smem)) return false;
+    if (!refine_gate<T>(s, k, ltr, Rr, Cc, g, G, grp, smem)) return false;
     if (g == 0 && threadIdx.x == 0) s.dims[k + 1] = s.ctr[CT_RANK];
     const bool ok = group_sync(grp);
     clk.lap(s.prof, PF_ABSORB);
