@@ -403,7 +403,10 @@ void nze_server_free(nze_server_t* s);
  * job could never fit the arena. */
 int nze_server_submit(nze_server_t* s, const nze_job_spec* spec, int64_t* job_id);
 /* Admission, one batched layer for every resident job, read-out of finished
- * jobs.  Outputs (may be NULL): resident jobs, queued jobs, finished jobs. */
+ * jobs.  Admission takes queued jobs in arrival order, first fit in the
+ * arena; a job that does not fit yet may be passed by later jobs that do, in
+ * at most 16 steps, after which nothing is admitted behind it until it fits.
+ * Outputs (may be NULL): resident jobs, queued jobs, finished jobs. */
 int nze_server_step(nze_server_t* s, int32_t* n_active, int32_t* n_queued,
                     int32_t* n_done);
 /* state: 0 queued, 1 resident, 2 done, < 0 error code.  When done, values

@@ -29,6 +29,7 @@ struct Job {
   std::vector<uint8_t> paulis;
   // run state
   int state = 0;                      // 0 queued, 1 resident, 2 done, <0 error
+  int passed = 0;                     // steps in which a later job was admitted first
   int layer = 0;
   mpo_t* h = nullptr;
   size_t off = 0, bytes = 0;          // arena block
@@ -37,6 +38,9 @@ struct Job {
 };
 
 }  // namespace
+
+// steps in which a queued job may be passed by later jobs that fit
+constexpr int BACKFILL_STEPS = 16;
 
 struct nze_server {
   char* arena = nullptr;
@@ -182,25 +186,41 @@ int finish(nze_server* s, Job* j) {
 extern "C" int nze_server_step(nze_server_t* s, int32_t* n_active,
                                int32_t* n_queued, int32_t* n_done) {
   if (!s) return fail(NZE_EINVAL, "NULL server");
-  // admission in arrival order, by HBM footprint
-  while (!s->queue.empty() && (int)s->active.size() < s->max_active) {
-    Job* j = s->queue.front();
-    const size_t need = mpo_footprint(&j->cfg);
-    size_t off;
-    if (!s->alloc(need, &off)) break;
-    int rc = mpo_init(&j->h, &j->cfg, nullptr, s->arena + off, need, s->stream);
-    if (rc != NZE_OK) {
-      s->release(off);
-      s->queue.pop_front();
-      j->state = rc;
-      continue;
+  // admission in arrival order, first fit in the arena by HBM footprint.
+  // A job that does not fit yet may be passed by later ones that do
+  // (backfill), in at most BACKFILL_STEPS steps; after that nothing is
+  // admitted behind it until it fits, so no job waits for ever.
+  {
+    std::vector<Job*> waiting;          // older jobs that did not fit this step
+    std::vector<Job*> keep;
+    bool passed_this_step = false;
+    bool closed = false;                // an old enough job blocks the rest
+    for (Job* j : s->queue) {
+      if (closed || (int)s->active.size() >= s->max_active) { keep.push_back(j); continue; }
+      const size_t need = mpo_footprint(&j->cfg);
+      size_t off;
+      if (!s->alloc(need, &off)) {
+        waiting.push_back(j);
+        keep.push_back(j);
+        if (j->passed >= BACKFILL_STEPS) closed = true;
+        continue;
+      }
+      int rc = mpo_init(&j->h, &j->cfg, nullptr, s->arena + off, need, s->stream);
+      if (rc != NZE_OK) {
+        s->release(off);
+        j->state = rc;
+        continue;
+      }
+      j->off = off;
+      j->bytes = need;
+      j->state = 1;
+      j->t_admit = s->now();
+      s->active.push_back(j);
+      passed_this_step = passed_this_step || !waiting.empty();
     }
-    j->off = off;
-    j->bytes = need;
-    j->state = 1;
-    j->t_admit = s->now();
-    s->queue.pop_front();
-    s->active.push_back(j);
+    if (passed_this_step)
+      for (Job* j : waiting) j->passed += 1;
+    s->queue.assign(keep.begin(), keep.end());
   }
   // one layer of every resident job, batched per precision.  A job's layer
   // counter advances once its launch is enqueued; a failing launch of several

@@ -555,6 +555,51 @@ def test_server_alone_vs_mix_bitwise(precision, tol):
             assert np.max(np.abs(mixed[j][1][lv] - m.expectations(obs))) < tol
 
 
+@pytest.mark.parametrize("precision", [nze.NZE_FP64, nze.NZE_MIXED])
+def test_server_backfill_admits_a_fitting_job_past_a_waiting_one(precision):
+    # an arena of exactly the second job's footprint: while the first job is
+    # resident the second cannot be admitted, and the third, which fits
+    # beside the first, is admitted before it (backfill); the second still
+    # runs once the first has released its memory, and every result equals
+    # the job run alone
+    noise = {"dep": 2e-3}
+    specs = [(8, 16, 4, 5, 41), (12, 64, 8, 6, 42), (8, 16, 2, 4, 43)]
+    jobs = []
+    for n, chi, L, depth, seed in specs:
+        layers = workloads.brickwork(n, depth, seed=seed)
+        factors = list(np.linspace(1.0, 4.0, L))
+        ptms = [nze.layer_ptms(us, noise, factors) for _, us in layers]
+        jobs.append((n, chi, [ls for ls, _ in layers], ptms, workloads.z_singles(n)))
+    fp = [nze.footprint(nze.make_config(n, chi, ptms[0].shape[0], precision))
+          for (n, chi, _, ptms, _) in jobs]
+    arena = fp[1]
+    assert fp[0] + fp[2] <= arena < fp[0] + fp[1]
+
+    def run(selection, arena_bytes):
+        srv = nze.Server(arena_bytes, max_active=8)
+        ids = [srv.submit(n, chi, precision, lss, ptms, obs)
+               for (n, chi, lss, ptms, obs) in selection]
+        for _ in range(200):
+            a, q, d = srv.step()
+            if d == len(ids):
+                break
+        out = [srv.poll(i) for i in ids]
+        srv.close()
+        return out
+
+    _say(f"backfill prec={precision}: footprints {fp}, arena {arena}")
+    mixed = run(jobs, arena)
+    assert all(st == 2 for st, _, _, _ in mixed)
+    t_admit = [t[1] for _, _, _, t in mixed]
+    t_done = [t[2] for _, _, _, t in mixed]
+    assert t_admit[2] < t_admit[1]          # the third job passed the second
+    assert t_admit[1] >= t_done[0]          # which waited for the first's memory
+    for j, job in enumerate(jobs):
+        alone = run([job], 64 << 20)[0]
+        assert np.array_equal(mixed[j][1], alone[1])
+        assert np.array_equal(mixed[j][2], alone[2])
+
+
 def test_plain_n8_extrapolation_both_readings():
     # n = 8 workload: extrapolated values from the GPU pipeline (readout +
     # host fit) equal the oracle's; their error against the dense density
