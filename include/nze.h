@@ -48,9 +48,11 @@ extern "C" {
 
 /* ------------------------------------------------------------- precision */
 #define NZE_FP64 0   /* every contraction and rotation in float64            */
-#define NZE_MIXED 1  /* float32 MFMA contractions/rotations; Jacobi rotation
-                        parameters, truncation decisions, fidelities, norms
-                        and readout in float64                               */
+#define NZE_MIXED 1  /* float32 sites, blocks and MFMA contractions/rotations;
+                        Jacobi rotation parameters, truncation decisions,
+                        the refinement of every update (orthonormal factor,
+                        projection, fidelities), norms and readout in
+                        float64                                              */
 
 /* ------------------------------------------------------------ fit methods */
 #define NZE_POLY 0      /* least-squares polynomial in lambda                 */
@@ -253,11 +255,10 @@ typedef struct nze_stats {
   double flops;          /* algorithmic flops executed so far: contraction
                             32 cl cm cr + superoperator 512 cl cr per update;
                             per Jacobi sweep on R rows of length C,
-                            4 R^2 (2C + R) (block Grams plus rotation of the
-                            data and of the accumulator; 8 R^2 C in the mixed
-                            path, which keeps no accumulator); centre-move
-                            absorption 8 r cr c2.  The float64 refinement of
-                            the mixed path is not counted                    */
+                            8 R^2 C (block Grams plus rotation of the data
+                            rows; no accumulator); centre-move absorption
+                            8 r cr c2.  The float64 refinement (Newton-Schulz,
+                            projection, band polish) is not counted          */
   int64_t cap_hits;      /* SVDs that reached max_sweeps while every pair was
                             within 1000x the tolerance (the rounding floor);
                             beyond that mpo_expect/mpo_sync report
@@ -265,7 +266,7 @@ typedef struct nze_stats {
   double cap_offdiag;    /* largest scaled off-diagonal, in units of the
                             tolerance, in the last sweep of any SVD that
                             reached max_sweeps (0 if none did)               */
-  int64_t ns_scaled;     /* mixed path: orthonormalisations of the float64
+  int64_t ns_scaled;     /* orthonormalisations of the float64
                             refinement whose start was too far from
                             orthonormal for the plain iteration (the scaled,
                             longer one was used)                              */

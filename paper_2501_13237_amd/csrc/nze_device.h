@@ -32,7 +32,7 @@ enum { CT_RANK = 0, CT_ERR = 1, CT_MAXSW = 2, CT_UPD = 3, CT_SWTOT = 4,
        CT_WVER = CT_BVER + 136, CT_NSFB = CT_WVER + 136, CT_COUNT = CT_NSFB + 1 };
 // CT_NSFB: orthonormalisations that needed the scaled (slow) iteration
 // CT_BVER / CT_WVER: per row block (<= 136), visits whose data rows / whose
-// accumulator rows are final
+// accumulator rows (kernel hook) are final
 enum { ERR_NOCONV = 1, ERR_NAN = 2, ERR_ABORT = 4 };
 
 // Everything one MPO (one noise level of one job) owns on the device.
@@ -42,22 +42,25 @@ struct Slot {
   double* scal;     // [SC_COUNT]
   int* ctr;         // [CT_COUNT]
   void* X;          // [m_cap * m_cap] two-site block / Jacobi data
-  void* W;          // [m_cap * m_cap] Jacobi accumulator (rows)
-  void* Rm;         // [chi_cap * chi_cap] factor absorbed by a centre move
+  void* W;          // [m_cap * m_cap] layer kernel: copy of the unrotated
+                    // block for the refinement; kernel hook: Jacobi
+                    // accumulator (rows)
   double* norms;    // [m_cap] squared row norms
   int* perm;        // [m_cap] kept rows, in decreasing norm
   double* sval;     // [m_cap] kept singular values
   int n, chi, site_cap, m_cap;
   double tau, tie, tol_rel, tol_abs;
   int max_sweeps;
-  int no_acc;       // 1: the Jacobi keeps no accumulator (the float64
-                    // refinement builds the orthonormal factor from the rows)
+  int no_acc;       // 1 (the layer kernel's MPOs): the Jacobi keeps no
+                    // accumulator, the float64 refinement builds the
+                    // orthonormal factor from the rows; 0 (kernel hook): the
+                    // rotations accumulate in W
   double* prof;     // [PROF_N] constant-rate clock ticks per phase (WG 0)
   // Jacobi schedule: the first cross_sweeps sweeps of problems with at least
   // cross_min_blocks row blocks take cross-block inner steps only
   int cross_sweeps, cross_min_blocks;
-  // float64 refinement workspace of the mixed path (nullptr: no refinement):
-  // [chi * m_cap] + [chi * chi] + [chi * m_cap] doubles
+  // float64 refinement workspace (both precisions):
+  // [(chi + 16) * m_cap] + [max((chi + 16)^2, 1088)] + [(chi + 16) * m_cap] doubles
   double* R64;
 };
 
@@ -268,9 +271,9 @@ __device__ inline bool group_sync(Group& grp) {
 // Dataflow between the pair visits of a Jacobi sweep: ver[b] counts the
 // visits of row block b.  A visit of round t may start once both of its
 // blocks have completed round t - 1 (ver >= base + t), instead of waiting
-// for every pair of the round.  Data rows and accumulator rows have counters
-// of their own, so the accumulator rotation of one visit overlaps the next
-// visits of the same blocks.
+// for every pair of the round.  In the kernel hook, which accumulates the
+// rotations, accumulator rows have counters of their own, so the
+// accumulator rotation of one visit overlaps the next visits of the blocks.
 __device__ inline bool blocks_wait(Group& grp, const int* ver, int I, int J,
                                    int target) {
   if (threadIdx.x == 0) {

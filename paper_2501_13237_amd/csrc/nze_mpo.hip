@@ -310,7 +310,7 @@ namespace {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t sites, X, W, Rm, norms, perm, sval, dims, scal, ctr, env, envlog, prof, r64, total;
+  size_t sites, X, W, norms, perm, sval, dims, scal, ctr, env, envlog, prof, r64, total;
 };
 
 // doubles of one slot's refinement workspace (the layout of r64_rows /
@@ -337,7 +337,6 @@ Layout layout_of(const mpo_config* c) {
   o.sites = take(L * n * site_cap * es);
   o.X = take(L * m * m * es);
   o.W = take(L * m * m * es);
-  o.Rm = take(L * chi * chi * es);
   o.norms = take(L * m * 8);
   o.perm = take(L * m * 4);
   o.sval = take(L * m * 8);
@@ -347,9 +346,9 @@ Layout layout_of(const mpo_config* c) {
   o.env = take(L * 2 * (n + 1) * chi * 8);
   o.envlog = take(L * 2 * (n + 1) * 8);
   o.prof = take(L * PF_N * 8);
-  // mixed path: float64 refinement workspace per level
-  // (chi + 16 rows: the kept directions and the polished band below the cut)
-  o.r64 = take(c->precision == NZE_MIXED ? L * r64_doubles(chi, m) * 8 : 0);
+  // float64 refinement workspace per level (chi + 16 rows: the kept
+  // directions and the polished band below the cut)
+  o.r64 = take(L * r64_doubles(chi, m) * 8);
   o.total = off;
   return o;
 }
@@ -597,7 +596,6 @@ extern "C" int mpo_init(mpo_t** out, const mpo_config* cfg,
     s.ctr = reinterpret_cast<int*>(h->ws + lay.ctr) + (size_t)l * CT_COUNT;
     s.X = h->ws + lay.X + (size_t)l * h->m_cap * h->m_cap * es;
     s.W = h->ws + lay.W + (size_t)l * h->m_cap * h->m_cap * es;
-    s.Rm = h->ws + lay.Rm + (size_t)l * c.chi_max * c.chi_max * es;
     s.norms = reinterpret_cast<double*>(h->ws + lay.norms) + (size_t)l * h->m_cap;
     s.perm = reinterpret_cast<int*>(h->ws + lay.perm) + (size_t)l * h->m_cap;
     s.sval = reinterpret_cast<double*>(h->ws + lay.sval) + (size_t)l * h->m_cap;
@@ -611,10 +609,8 @@ extern "C" int mpo_init(mpo_t** out, const mpo_config* cfg,
     s.tol_abs = c.jacobi_abs;
     s.max_sweeps = c.max_sweeps;
     s.prof = reinterpret_cast<double*>(h->ws + lay.prof) + (size_t)l * PF_N;
-    s.R64 = c.precision == NZE_MIXED
-                ? reinterpret_cast<double*>(h->ws + lay.r64) + (size_t)l * r64_doubles(c.chi_max, h->m_cap)
-                : nullptr;
-    s.no_acc = c.precision == NZE_MIXED ? 1 : 0;
+    s.R64 = reinterpret_cast<double*>(h->ws + lay.r64) + (size_t)l * r64_doubles(c.chi_max, h->m_cap);
+    s.no_acc = 1;
     s.cross_sweeps = have_tune ? tune_rec.cross_sweeps : 8;
     s.cross_min_blocks = have_tune ? tune_rec.cross_min_blocks : 64;
     h->slots.push_back(s);
@@ -763,8 +759,8 @@ int launch_plans(mpo_t* const* hs, int k, const std::vector<std::vector<Step>>& 
   }
   // A batch that asks for at most half of the CUs gets its groups doubled
   // (still one workgroup per CU): consecutive Jacobi rounds then alternate
-  // between two sets of workgroups, and the accumulator rotation of one round
-  // runs beside the next round's data visits.  Two such workgroups sharing a
+  // between two sets of workgroups, so a round's visits start on workgroups
+  // that are not finishing the round before.  Two such workgroups sharing a
   // CU gain nothing (measured), hence only on idle CUs.
   const bool can_double = want_tot * 2 <= (long long)resident;
   const bool dbl = ch.group_scale ? (ch.group_scale == 2 && can_double)
@@ -1247,7 +1243,7 @@ extern "C" int mpo_overlap(mpo_t* a, int32_t la, mpo_t* b, int32_t lb,
     rc = read_errors(b);
     if (rc) return rc;
   }
-  // scratch: the two-site and accumulator blocks of the handle with the larger
+  // scratch: the two-site block and its copy (W) of the handle with the larger
   // chi cap, idle between layer launches (both streams were synchronised)
   mpo_t* s = b->cfg.chi_max >= a->cfg.chi_max ? b : a;
   const size_t es = s->cfg.precision == NZE_FP64 ? 8 : 4;

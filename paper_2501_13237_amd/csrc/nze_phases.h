@@ -3,20 +3,25 @@
 //
 // Update of the gate on (k, k+1) (Sec. 2.1.2 "Approximate emulation"):
 //   theta   Theta' = (R x 1)(M_k M_{k+1}) written as the row-major matrix X
-//           (rows (a,p'), cols (q',b) left to right; its transpose right to
-//           left), W = I, F2 = ||X||_F^2                         [MFMA]
-//   jacobi  block one-sided Jacobi on the rows of X, accumulating the
-//           rotations in W: afterwards W X has orthogonal rows whose norms
-//           are the singular values                               [MFMA + LDS]
+//           in the orientation whose rows carry the factor that stays
+//           orthonormal (rows (q',b) left to right, (a,p') right to left),
+//           with a copy of it in W                               [MFMA]
+//   jacobi  block one-sided Jacobi on the rows of X (no accumulator):
+//           afterwards X has orthogonal rows s_i (singular vector)^T
+//                                                                 [MFMA + LDS]
 //   norms   squared row norms in float64
-//   select  sort, truncation rank r, partial fidelity f = kept / total,
-//           emulation fidelity *= f, log-scale, statistics      [one WG]
-//   absorb  left to right: M_k = W rows (U_r), M_{k+1} = X rows / ||kept||
-//           (S_r V_r^T); right to left mirrored
+//   select  sort, truncation rank r (tie rule), kept-row order  [one WG]
+//   refine  float64: the kept rows divided by their norms, orthonormalised
+//           (Newton-Schulz), give the orthonormal factor Q; the other factor
+//           is the projection Y = Q X0^T of the unrotated block; a
+//           Rayleigh-Ritz polish of the directions around a chi cut; partial
+//           fidelity f = kept / total, emulation fidelity *= f, log-scale;
+//           the two new sites from Q and Y / ||kept||
 // Centre move (the canonical form of App. A.1's footnote): the same Jacobi on
 // the centre site viewed as (chi_r x 4 chi_l) (left to right) or
-// (chi_l x 4 chi_r) (right to left), then the orthonormal factor stays and
-// S W is multiplied into the neighbour.
+// (chi_l x 4 chi_r) (right to left), then the orthonormal factor from the
+// kept rows (float64, as above) stays and the projection of the site onto it
+// is multiplied into the neighbour in float64.
 #ifndef NZE_PHASES_H
 #define NZE_PHASES_H
 
@@ -29,85 +34,6 @@ namespace nze {
 template <typename T>
 __device__ inline T* site_ptr(const Slot& s, int k) {
   return reinterpret_cast<T*>(s.sites) + (size_t)k * s.site_cap;
-}
-
-// 64x64-tile GEMM C = A B (row-major, all operands in path precision) over
-// the group's workgroups.  Wave w owns rows [16w, 16w+16) of a tile.
-template <typename T>
-__device__ __forceinline__ void gemm_nn(const T* A, int lda, const T* B, int ldb, T* C, int ldc,
-                        int M, int N, int K, int g, int G) {
-  typedef typename AccT<T>::type acc_t;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i = lane & 15, kq = lane >> 4;
-  const int tm = (M + 63) / 64, tn = (N + 63) / 64;
-  for (int tile = g; tile < tm * tn; tile += G) {
-    const int m0 = (tile / tn) * 64, n0 = (tile % tn) * 64;
-    const int row = m0 + 16 * w + i;
-    acc_t acc[4];
-    for (int j = 0; j < 4; ++j) acc[j] = acc_t{0, 0, 0, 0};
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      const int c = k0 + kq;
-      const T av = (row < M && c < K) ? A[(size_t)row * lda + c] : T(0);
-      for (int j = 0; j < 4; ++j) {
-        const int col = n0 + 16 * j + i;
-        const T bv = (c < K && col < N) ? B[(size_t)c * ldb + col] : T(0);
-        acc[j] = mfma4(av, bv, acc[j]);
-      }
-    }
-    for (int j = 0; j < 4; ++j)
-      for (int r = 0; r < 4; ++r) {
-        const int rr = m0 + 16 * w + mrow<T>(kq, r), cc = n0 + 16 * j + i;
-        if (rr < M && cc < N) C[(size_t)rr * ldc + cc] = acc[j][r];
-      }
-  }
-}
-
-// dst[a][i] = src[perm[i]][a] * scale_i  for a < na, i < r   (LDS transpose)
-// mode 0: scale = cst; 1: cst * sv[i]; 2: cst / sv[i]
-template <typename T>
-__device__ __forceinline__ void gather_t(const T* src, int lds, const int* perm, int na, int r,
-                         T* dst, int ldd, const double* sv, int mode,
-                         double cst, int g, int G, double* smem) {
-  T* tile = reinterpret_cast<T*>(smem);   // [32][33]
-  const int ta = (na + 31) / 32, ti = (r + 31) / 32;
-  for (int t = g; t < ta * ti; t += G) {
-    const int a0 = (t / ti) * 32, i0 = (t % ti) * 32;
-    __syncthreads();
-    for (int e = threadIdx.x; e < 1024; e += NT) {
-      const int ii = e >> 5, al = e & 31;
-      T v = T(0);
-      if (i0 + ii < r && a0 + al < na) {
-        double sc = cst;
-        if (mode == 1) sc *= sv[i0 + ii];
-        else if (mode == 2) sc /= sv[i0 + ii];
-        v = T(src[(size_t)perm[i0 + ii] * lds + a0 + al] * sc);
-      }
-      tile[ii * 33 + al] = v;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < 1024; e += NT) {
-      const int al = e >> 5, ii = e & 31;
-      if (i0 + ii < r && a0 + al < na)
-        dst[(size_t)(a0 + al) * ldd + i0 + ii] = tile[ii * 33 + al];
-    }
-  }
-  __syncthreads();
-}
-
-// dst[i][c] = src[perm[i]][c] * scale_i  for i < r, c < nc
-template <typename T>
-__device__ __forceinline__ void gather_r(const T* src, int lds, const int* perm, int r, int nc,
-                         T* dst, int ldd, const double* sv, int mode,
-                         double cst, int g, int G) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  for (int i = g * 4 + w; i < r; i += 4 * G) {
-    double sc = cst;
-    if (mode == 1) sc *= sv[i];
-    else if (mode == 2) sc /= sv[i];
-    const T* s = src + (size_t)perm[i] * lds;
-    T* d = dst + (size_t)i * ldd;
-    for (int c = lane; c < nc; c += 64) d[c] = T(s[c] * sc);
-  }
 }
 
 // W = I (n x n), distributed by rows.
@@ -922,18 +848,20 @@ __device__ __forceinline__ void phase_select(const Slot& s, int R, bool gate, do
   for (int i = tid; i < MAXSW; i += NT) s.ctr[CT_ROT + i] = 0;
 }
 
-// ------------------------------------------- float64 refinement (mixed)
+// ------------------------------------------------ float64 refinement
 //
-// The float32 Jacobi leaves two kinds of error that matter for a truncated
-// state: its accumulator rows are orthonormal only to the float32 rounding
-// it has gathered (a few 1e-6 after a dozen sweeps), and its rotated data
-// rows carry absolute rounding of order eps ||X||.  The refinement keeps the
-// float32 decisions (rank, kept directions) and rebuilds the two factors in
-// float64: the kept orthonormal rows get one Newton-Schulz step
-// Q <- (3 I - Q Q^T) Q / 2 (quadratic: 1e-6 -> 1e-12), and the other factor is
-// the projection of the unrotated block onto them.  The product of the two
-// factors is then the orthogonal projection of the block onto the kept
-// subspace, and the partial fidelity kept / total is exactly that
+// The Jacobi keeps no accumulator: its rotated rows are s_i times a singular
+// vector plus rounding of order eps ||X|| (eps of the row precision), so the
+// direction of a row with a small s_i carries a relative error of order
+// eps s_1 / s_i.  The refinement keeps the Jacobi's decisions (rank, kept
+// rows) and rebuilds the two factors in float64: the kept rows divided by
+// their norms, orthonormalised by Newton-Schulz iterations
+// Q <- (3 I - Q Q^T) Q / 2, give the orthonormal factor, and the other factor
+// is the projection of the unrotated block onto it (no division by singular
+// values).  The product of the two factors is then the orthogonal projection
+// of the block onto the kept span: a direction error theta_ij between kept
+// row i and dropped direction j changes the state by theta_ij s_j <= eps s_1
+// (s_j <= s_i), and the partial fidelity kept / total is exactly that
 // projection's (Sec. 2.1.2, eq. for f_l).
 
 // C (M x N, float64, row-major ldc) = A op(B) over the group's workgroups on
@@ -1197,8 +1125,8 @@ __device__ inline void band_rotate(double* M, int ld, int n, int b0, int nb, con
   __syncthreads();
 }
 
-// Gate update after phase_select(defer), from the rows of the float32
-// Jacobi alone.  The Jacobi ran on the block oriented so that its rows carry
+// Gate update after phase_select(defer), from the rows of the Jacobi
+// alone.  The Jacobi ran on the block oriented so that its rows carry
 // the factor that stays orthonormal: left to right the rows of Theta'^T
 // (indexed (q', b)), whose rotated rows are s_i u_i^T; right to left the rows
 // of Theta' (indexed (a, p')), whose rotated rows are s_i v_i^T.  The kept
@@ -1207,7 +1135,7 @@ __device__ inline void band_rotate(double* M, int ld, int n, int b0, int nb, con
 // unrotated block X0 (the copy the contraction left in W), Y = Q X0^T.  A
 // float64 Rayleigh-Ritz polish of the BAND
 // kept and BAND dropped directions around a chi cut resolves the mixing the
-// float32 Jacobi leaves between near-degenerate directions there (about
+// Jacobi leaves between near-degenerate directions there (about
 // tol / (2 relative gap)), and the tie rule is re-decided on its values.
 // Returns 1 when done, 0 on a barrier failure.
 template <typename T>
@@ -1382,19 +1310,17 @@ template <typename T, int VEC = 1>
 __device__ __forceinline__ bool op_gate(const Slot& s, int k, bool ltr, const double* R, int g,
                         int G, Group& grp, double* smem) {
   const int cl = s.dims[k], cr = s.dims[k + 2];
-  // with the float64 refinement (float32 path) the Jacobi keeps no
-  // accumulator and runs on the orientation whose rows carry the factor that
-  // stays orthonormal (refine_gate); otherwise rows (a, p') left to right
-  bool refine = false;
-  if constexpr (sizeof(T) == 4) refine = s.R64 != nullptr && s.no_acc;
-  const bool rows_ap = refine ? !ltr : ltr;
+  // the Jacobi keeps no accumulator and runs on the orientation whose rows
+  // carry the factor that stays orthonormal (rows (q', b) left to right,
+  // (a, p') right to left); refine_gate builds both factors in float64
+  const bool rows_ap = !ltr;
   const int Rr = rows_ap ? 4 * cl : 4 * cr, Cc = rows_ap ? 4 * cr : 4 * cl;
   T* X = reinterpret_cast<T*>(s.X);
   T* W = reinterpret_cast<T*>(s.W);
   PhaseClock clk(g == 0 && s.prof != nullptr);
-  // (the refinement keeps a copy of the unrotated block in W, which the
-  // Jacobi without accumulator leaves free)
-  phase_theta<T>(s, k, rows_ap, R, g, G, smem, true, !s.no_acc, refine ? W : nullptr);
+  // the contraction keeps a copy of the unrotated block in W for the
+  // refinement's projection
+  phase_theta<T>(s, k, rows_ap, R, g, G, smem, true, false, W);
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_THETA);
   if (!phase_jacobi<T, VEC>(s, X, W, Rr, Cc, g, G, grp, smem)) return false;
@@ -1402,29 +1328,11 @@ __device__ __forceinline__ bool op_gate(const Slot& s, int k, bool ltr, const do
   phase_norms<T>(s, X, Rr, Cc, g, G);
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_NORMS);
-  if (g == 0) phase_select(s, Rr, true, smem, refine);
+  if (g == 0) phase_select(s, Rr, true, smem, true);
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_SELECT);
-  if constexpr (sizeof(T) == 4) if (refine) {
-    if (!refine_gate<T>(s, k, ltr, Rr, Cc, g, G, grp, smem)) return false;
-    if (g == 0 && threadIdx.x == 0) s.dims[k + 1] = s.ctr[CT_RANK];
-    const bool ok = group_sync(grp);
-    clk.lap(s.prof, PF_ABSORB);
-    return ok;
-  }
-  const int r = s.ctr[CT_RANK];
-  const double inv = 1.0 / sqrt(s.scal[SC_KEPT]);
-  T* Mk = site_ptr<T>(s, k);
-  T* Mk1 = site_ptr<T>(s, k + 1);
-  if (ltr) {
-    gather_t<T>(W, Rr, s.perm, 4 * cl, r, Mk, r, nullptr, 0, 1.0, g, G, smem);
-    gather_r<T>(X, Cc, s.perm, r, 4 * cr, Mk1, 4 * cr, nullptr, 0, inv, g, G);
-  } else {
-    gather_t<T>(X, Cc, s.perm, 4 * cl, r, Mk, r, nullptr, 0, inv, g, G, smem);
-    gather_r<T>(W, Rr, s.perm, r, 4 * cr, Mk1, 4 * cr, nullptr, 0, 1.0, g, G);
-  }
-  if (!group_sync(grp)) return false;
-  if (g == 0 && threadIdx.x == 0) s.dims[k + 1] = r;
+  if (!refine_gate<T>(s, k, ltr, Rr, Cc, g, G, grp, smem)) return false;
+  if (g == 0 && threadIdx.x == 0) s.dims[k + 1] = s.ctr[CT_RANK];
   const bool ok = group_sync(grp);
   clk.lap(s.prof, PF_ABSORB);
   return ok;
@@ -1451,7 +1359,6 @@ __device__ __forceinline__ bool op_move(const Slot& s, int c, bool ltr, int g, i
   const int cl = s.dims[c], cr = s.dims[c + 1];
   T* X = reinterpret_cast<T*>(s.X);
   T* W = reinterpret_cast<T*>(s.W);
-  T* Rm = reinterpret_cast<T*>(s.Rm);
   T* M = site_ptr<T>(s, c);
   const int Rr = ltr ? cr : cl, Cc = ltr ? 4 * cl : 4 * cr;
   PhaseClock clk(g == 0 && s.prof != nullptr);
@@ -1486,7 +1393,6 @@ __device__ __forceinline__ bool op_move(const Slot& s, int c, bool ltr, int g, i
           X[(size_t)r * Cc + cc] = v;
         }
     }
-    if (!s.no_acc) set_identity(W, Rr, g, G);
   }
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_MOVE_PREP);
@@ -1497,48 +1403,7 @@ __device__ __forceinline__ bool op_move(const Slot& s, int c, bool ltr, int g, i
   if (g == 0) phase_select(s, Rr, false, smem);
   if (!group_sync(grp)) return false;
   clk.lap(s.prof, PF_SELECT);
-  if constexpr (sizeof(T) == 4) if (s.R64 != nullptr && s.no_acc) {
-    const bool ok = refine_move<T>(s, c, ltr, Rr, Cc, g, G, grp, smem) == 1;
-    clk.lap(s.prof, PF_MOVE_GEMM);
-    return ok;
-  }
-  const int r = s.ctr[CT_RANK];
-  if (ltr) {
-    // M_c = Y^T S^-1 (4cl x r);  Rm = S W_perm (r x cr)
-    gather_t<T>(X, Cc, s.perm, 4 * cl, r, M, r, s.sval, 2, 1.0, g, G, smem);
-    gather_r<T>(W, Rr, s.perm, r, cr, Rm, cr, s.sval, 1, 1.0, g, G);
-  } else {
-    // M_c = S^-1 Y (r x 4cr);  Lm = W_perm^T S (cl x r)
-    gather_r<T>(X, Cc, s.perm, r, 4 * cr, M, 4 * cr, s.sval, 2, 1.0, g, G);
-    gather_t<T>(W, Rr, s.perm, cl, r, Rm, r, s.sval, 1, 1.0, g, G, smem);
-  }
-  if (!group_sync(grp)) return false;
-  if (ltr) {
-    const int c2 = s.dims[c + 2];
-    T* Mn = site_ptr<T>(s, c + 1);          // cr x 4c2
-    gemm_nn<T>(Rm, cr, Mn, 4 * c2, X, 4 * c2, r, 4 * c2, cr, g, G);
-    if (g == 0 && threadIdx.x == 0) s.scal[SC_FLOPS] += 8.0 * r * cr * c2;
-    if (!group_sync(grp)) return false;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int i = g * 4 + w; i < r; i += 4 * G)
-      for (int cc = lane; cc < 4 * c2; cc += 64)
-        Mn[(size_t)i * 4 * c2 + cc] = X[(size_t)i * 4 * c2 + cc];
-    if (!group_sync(grp)) return false;
-    if (g == 0 && threadIdx.x == 0) s.dims[c + 1] = r;
-  } else {
-    const int c0 = s.dims[c - 1];
-    T* Mp = site_ptr<T>(s, c - 1);          // 4c0 x cl
-    gemm_nn<T>(Mp, cl, Rm, r, X, r, 4 * c0, r, cl, g, G);
-    if (g == 0 && threadIdx.x == 0) s.scal[SC_FLOPS] += 8.0 * c0 * cl * r;
-    if (!group_sync(grp)) return false;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int i = g * 4 + w; i < 4 * c0; i += 4 * G)
-      for (int cc = lane; cc < r; cc += 64)
-        Mp[(size_t)i * r + cc] = X[(size_t)i * r + cc];
-    if (!group_sync(grp)) return false;
-    if (g == 0 && threadIdx.x == 0) s.dims[c] = r;
-  }
-  const bool ok = group_sync(grp);
+  const bool ok = refine_move<T>(s, c, ltr, Rr, Cc, g, G, grp, smem) == 1;
   clk.lap(s.prof, PF_MOVE_GEMM);
   return ok;
 }
