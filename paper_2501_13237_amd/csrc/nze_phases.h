@@ -286,6 +286,14 @@ __device__ inline void jacobi_cs(double gpp, double gqq, double gpq,
   sn = ra ? xa * ca : 0.0;
 }
 
+// v moved down by one lane inside each row of 16 lanes: lane l takes the
+// value of lane 16 (l / 16) + (l + 1) % 16 (DPP row rotate right by 15).
+__device__ __forceinline__ double row_next(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x12F, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x12F, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
 // One cyclic parallel Jacobi sweep on the 32x32 symmetric Gram in Ga
 // (float64, LDS), cross-block steps first (both blocks enter with nearly
 // orthogonal rows once a sweep has visited them, so the cross entries carry
@@ -296,7 +304,11 @@ __device__ inline void jacobi_cs(double gpp, double gqq, double gpq,
 // row pair P = t/16 = 4 w + l/16 comes from lane P of the same wave, which
 // computed it as its own column pair from the same values with the same
 // instructions.  G ping-pongs between Ga and Gb (swapped on return, Ga holds
-// the result): one workgroup barrier a step.  With cross_only the sweep
+// the result): one workgroup barrier a step.  In the cross-block steps the
+// block-I column of a thread's column pair stays P2 and the block-J column
+// moves from pair P2 + 1 to pair P2, so the thread keeps its two rows of Qs
+// at those columns in registers and takes the block-J entries from the next
+// lane of its 16-lane row (row_next); Qs is written back after them.  With cross_only the sweep
 // stops after the 16 cross-block steps.  Pivots with |g_pq| <= floor_abs are
 // not rotated.
 // skip_tol > 0: after the cross-block steps, the intra-block steps run only
@@ -312,12 +324,16 @@ __device__ __forceinline__ void gram_sweep32(const PairLds& L, double*& Ga, doub
   if (tid == 0) L.flag[0] = 0;   // ordered by the barrier of the first step
   const int P = tid >> 4, P2 = tid & 15, u0 = 2 * P;
   const int srcP = P & 15;
-  auto step = [&](int p, int q, int p2, int q2) {
+  // qreg: the cross-block steps' Qs entries, in registers
+  double qa = 0.0, qb = 0.0, qc = 0.0, qd = 0.0;
+  auto step = [&](int p, int q, int p2, int q2, bool qreg) {
     const double bpp = Ga[p2 * GLD + p2], bqq = Ga[q2 * GLD + q2], bpq = Ga[p2 * GLD + q2];
     const double g11 = Ga[p * GLD + p2], g12 = Ga[p * GLD + q2];
     const double g21 = Ga[q * GLD + p2], g22 = Ga[q * GLD + q2];
-    const double qa = L.Qs[u0 * GLD + p2], qb = L.Qs[u0 * GLD + q2];
-    const double qc = L.Qs[(u0 + 1) * GLD + p2], qd = L.Qs[(u0 + 1) * GLD + q2];
+    if (!qreg) {
+      qa = L.Qs[u0 * GLD + p2]; qb = L.Qs[u0 * GLD + q2];
+      qc = L.Qs[(u0 + 1) * GLD + p2]; qd = L.Qs[(u0 + 1) * GLD + q2];
+    }
     double c2, s2;
     jacobi_cs(bpp, bqq, bpq, floor_abs, c2, s2);
     const double c = __shfl(c2, srcP, 64), sn = __shfl(s2, srcP, 64);
@@ -327,18 +343,34 @@ __device__ __forceinline__ void gram_sweep32(const PairLds& L, double*& Ga, doub
     Gb[p * GLD + q2] = s2 * h11 + c2 * h12;
     Gb[q * GLD + p2] = c2 * h21 - s2 * h22;
     Gb[q * GLD + q2] = s2 * h21 + c2 * h22;
-    L.Qs[u0 * GLD + p2] = c2 * qa - s2 * qb;
-    L.Qs[u0 * GLD + q2] = s2 * qa + c2 * qb;
-    L.Qs[(u0 + 1) * GLD + p2] = c2 * qc - s2 * qd;
-    L.Qs[(u0 + 1) * GLD + q2] = s2 * qc + c2 * qd;
+    const double na = c2 * qa - s2 * qb, nb = s2 * qa + c2 * qb;
+    const double nc = c2 * qc - s2 * qd, nd = s2 * qc + c2 * qd;
+    if (qreg) {
+      qa = na; qb = nb; qc = nc; qd = nd;
+    } else {
+      L.Qs[u0 * GLD + p2] = na;
+      L.Qs[u0 * GLD + q2] = nb;
+      L.Qs[(u0 + 1) * GLD + p2] = nc;
+      L.Qs[(u0 + 1) * GLD + q2] = nd;
+    }
     double* t = Ga; Ga = Gb; Gb = t;
     __syncthreads();
   };
   // pairing of the 32 rows (rows 0-15: block I, 16-31: block J), 16
   // disjoint rotations a step: steps 0-15 pair row k of I with row
   // 16 + (k + st) mod 16 of J (all 256 cross pairs) ...
-  for (int st = 0; st < 16; ++st)
-    step(P, 16 + ((P + st) & 15), P2, 16 + ((P2 + st) & 15));
+  qa = L.Qs[u0 * GLD + P2]; qb = L.Qs[u0 * GLD + 16 + P2];
+  qc = L.Qs[(u0 + 1) * GLD + P2]; qd = L.Qs[(u0 + 1) * GLD + 16 + P2];
+  for (int st = 0; st < 16; ++st) {
+    step(P, 16 + ((P + st) & 15), P2, 16 + ((P2 + st) & 15), true);
+    if (st < 15) { qb = row_next(qb); qd = row_next(qd); }
+  }
+  {
+    const int jc = 16 + ((P2 + 15) & 15);
+    L.Qs[u0 * GLD + P2] = qa; L.Qs[u0 * GLD + jc] = qb;
+    L.Qs[(u0 + 1) * GLD + P2] = qc; L.Qs[(u0 + 1) * GLD + jc] = qd;
+    __syncthreads();
+  }
   if (cross_only) return;
   if (skip_tol > 0.0) {
     // thread t: entry (t / 16, t % 16) of each block's 16 x 16 corner
@@ -370,7 +402,8 @@ __device__ __forceinline__ void gram_sweep32(const PairLds& L, double*& Ga, doub
     const int bP = P < 8 ? 0 : 16, jP = P & 7, bQ = P2 < 8 ? 0 : 16, jQ = P2 & 7;
     int aP = jP == 0 ? 0 : jP - 1, cP = 14 - jP, aQ = jQ == 0 ? 0 : jQ - 1, cQ = 14 - jQ;
     for (int r = 0; r < 15; ++r) {
-      step(bP + (jP == 0 ? 0 : 1 + aP), bP + 1 + cP, bQ + (jQ == 0 ? 0 : 1 + aQ), bQ + 1 + cQ);
+      step(bP + (jP == 0 ? 0 : 1 + aP), bP + 1 + cP, bQ + (jQ == 0 ? 0 : 1 + aQ), bQ + 1 + cQ,
+         false);
       aP = aP == 14 ? 0 : aP + 1;
       cP = cP == 14 ? 0 : cP + 1;
       aQ = aQ == 14 ? 0 : aQ + 1;
