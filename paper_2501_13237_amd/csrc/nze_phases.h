@@ -305,11 +305,14 @@ __device__ __forceinline__ double row_next(double v) {
 // computed it as its own column pair from the same values with the same
 // instructions.  G ping-pongs between Ga and Gb (swapped on return, Ga holds
 // the result): one workgroup barrier a step.  In the cross-block steps the
-// block-I column of a thread's column pair stays P2 and the block-J column
-// moves from pair P2 + 1 to pair P2, so the thread keeps its two rows of Qs
-// at those columns in registers and takes the block-J entries from the next
-// lane of its 16-lane row (row_next); Qs is written back after them.  With cross_only the sweep
-// stops after the 16 cross-block steps.  Pivots with |g_pq| <= floor_abs are
+// block-I row and column of a thread's pairs stay P and P2, and the block-J
+// column moves from pair P2 + 1 to pair P2: the thread keeps its two rows of
+// Qs at its columns, and its entries G[P][P2] and G[P][J], in registers,
+// taking the block-J ones from the next lane of its 16-lane row (row_next);
+// only the block-J rows of G pass through LDS, plus the entries that are
+// the next step's pivots (G[P][P] and G[P][J] of pair P + 1), and all of G
+// and Qs after the last of these steps.  With cross_only the sweep stops
+// after the 16 cross-block steps.  Pivots with |g_pq| <= floor_abs are
 // not rotated.
 // skip_tol > 0: after the cross-block steps, the intra-block steps run only
 // if some intra-block entry fails the visit's convergence test
@@ -324,16 +327,12 @@ __device__ __forceinline__ void gram_sweep32(const PairLds& L, double*& Ga, doub
   if (tid == 0) L.flag[0] = 0;   // ordered by the barrier of the first step
   const int P = tid >> 4, P2 = tid & 15, u0 = 2 * P;
   const int srcP = P & 15;
-  // qreg: the cross-block steps' Qs entries, in registers
-  double qa = 0.0, qb = 0.0, qc = 0.0, qd = 0.0;
-  auto step = [&](int p, int q, int p2, int q2, bool qreg) {
+  auto step = [&](int p, int q, int p2, int q2) {
     const double bpp = Ga[p2 * GLD + p2], bqq = Ga[q2 * GLD + q2], bpq = Ga[p2 * GLD + q2];
     const double g11 = Ga[p * GLD + p2], g12 = Ga[p * GLD + q2];
     const double g21 = Ga[q * GLD + p2], g22 = Ga[q * GLD + q2];
-    if (!qreg) {
-      qa = L.Qs[u0 * GLD + p2]; qb = L.Qs[u0 * GLD + q2];
-      qc = L.Qs[(u0 + 1) * GLD + p2]; qd = L.Qs[(u0 + 1) * GLD + q2];
-    }
+    const double qa = L.Qs[u0 * GLD + p2], qb = L.Qs[u0 * GLD + q2];
+    const double qc = L.Qs[(u0 + 1) * GLD + p2], qd = L.Qs[(u0 + 1) * GLD + q2];
     double c2, s2;
     jacobi_cs(bpp, bqq, bpq, floor_abs, c2, s2);
     const double c = __shfl(c2, srcP, 64), sn = __shfl(s2, srcP, 64);
@@ -343,33 +342,49 @@ __device__ __forceinline__ void gram_sweep32(const PairLds& L, double*& Ga, doub
     Gb[p * GLD + q2] = s2 * h11 + c2 * h12;
     Gb[q * GLD + p2] = c2 * h21 - s2 * h22;
     Gb[q * GLD + q2] = s2 * h21 + c2 * h22;
-    const double na = c2 * qa - s2 * qb, nb = s2 * qa + c2 * qb;
-    const double nc = c2 * qc - s2 * qd, nd = s2 * qc + c2 * qd;
-    if (qreg) {
-      qa = na; qb = nb; qc = nc; qd = nd;
-    } else {
-      L.Qs[u0 * GLD + p2] = na;
-      L.Qs[u0 * GLD + q2] = nb;
-      L.Qs[(u0 + 1) * GLD + p2] = nc;
-      L.Qs[(u0 + 1) * GLD + q2] = nd;
-    }
+    L.Qs[u0 * GLD + p2] = c2 * qa - s2 * qb;
+    L.Qs[u0 * GLD + q2] = s2 * qa + c2 * qb;
+    L.Qs[(u0 + 1) * GLD + p2] = c2 * qc - s2 * qd;
+    L.Qs[(u0 + 1) * GLD + q2] = s2 * qc + c2 * qd;
     double* t = Ga; Ga = Gb; Gb = t;
     __syncthreads();
   };
   // pairing of the 32 rows (rows 0-15: block I, 16-31: block J), 16
   // disjoint rotations a step: steps 0-15 pair row k of I with row
-  // 16 + (k + st) mod 16 of J (all 256 cross pairs) ...
-  qa = L.Qs[u0 * GLD + P2]; qb = L.Qs[u0 * GLD + 16 + P2];
-  qc = L.Qs[(u0 + 1) * GLD + P2]; qd = L.Qs[(u0 + 1) * GLD + 16 + P2];
-  for (int st = 0; st < 16; ++st) {
-    step(P, 16 + ((P + st) & 15), P2, 16 + ((P2 + st) & 15), true);
-    if (st < 15) { qb = row_next(qb); qd = row_next(qd); }
-  }
+  // 16 + (k + st) mod 16 of J (all 256 cross pairs) ...  (the arithmetic of
+  // step(), with the entries that stay on a thread in registers)
   {
-    const int jc = 16 + ((P2 + 15) & 15);
-    L.Qs[u0 * GLD + P2] = qa; L.Qs[u0 * GLD + jc] = qb;
-    L.Qs[(u0 + 1) * GLD + P2] = qc; L.Qs[(u0 + 1) * GLD + jc] = qd;
-    __syncthreads();
+    double qa = L.Qs[u0 * GLD + P2], qb = L.Qs[u0 * GLD + 16 + P2];
+    double qc = L.Qs[(u0 + 1) * GLD + P2], qd = L.Qs[(u0 + 1) * GLD + 16 + P2];
+    double g11 = Ga[P * GLD + P2], g12 = Ga[P * GLD + 16 + P2];
+    const bool piv11 = P == P2, piv12 = P2 == ((P + 1) & 15);
+    for (int st = 0; st < 16; ++st) {
+      const int p = P, q = 16 + ((P + st) & 15), p2 = P2, q2 = 16 + ((P2 + st) & 15);
+      const double bpp = Ga[p2 * GLD + p2], bqq = Ga[q2 * GLD + q2], bpq = Ga[p2 * GLD + q2];
+      const double g21 = Ga[q * GLD + p2], g22 = Ga[q * GLD + q2];
+      double c2, s2;
+      jacobi_cs(bpp, bqq, bpq, floor_abs, c2, s2);
+      const double c = __shfl(c2, srcP, 64), sn = __shfl(s2, srcP, 64);
+      const double h11 = c * g11 - sn * g21, h12 = c * g12 - sn * g22;
+      const double h21 = sn * g11 + c * g21, h22 = sn * g12 + c * g22;
+      const double n11 = c2 * h11 - s2 * h12, n12 = s2 * h11 + c2 * h12;
+      Gb[q * GLD + p2] = c2 * h21 - s2 * h22;
+      Gb[q * GLD + q2] = s2 * h21 + c2 * h22;
+      if (st == 15 || piv11) Gb[p * GLD + p2] = n11;
+      if (st == 15 || piv12) Gb[p * GLD + q2] = n12;
+      const double na = c2 * qa - s2 * qb, nb = s2 * qa + c2 * qb;
+      const double nc = c2 * qc - s2 * qd, nd = s2 * qc + c2 * qd;
+      qa = na; qc = nc; g11 = n11;
+      if (st < 15) {
+        qb = row_next(nb); qd = row_next(nd); g12 = row_next(n12);
+      } else {
+        const int jc = 16 + ((P2 + 15) & 15);
+        L.Qs[u0 * GLD + P2] = na; L.Qs[u0 * GLD + jc] = nb;
+        L.Qs[(u0 + 1) * GLD + P2] = nc; L.Qs[(u0 + 1) * GLD + jc] = nd;
+      }
+      double* t = Ga; Ga = Gb; Gb = t;
+      __syncthreads();
+    }
   }
   if (cross_only) return;
   if (skip_tol > 0.0) {
@@ -402,8 +417,7 @@ __device__ __forceinline__ void gram_sweep32(const PairLds& L, double*& Ga, doub
     const int bP = P < 8 ? 0 : 16, jP = P & 7, bQ = P2 < 8 ? 0 : 16, jQ = P2 & 7;
     int aP = jP == 0 ? 0 : jP - 1, cP = 14 - jP, aQ = jQ == 0 ? 0 : jQ - 1, cQ = 14 - jQ;
     for (int r = 0; r < 15; ++r) {
-      step(bP + (jP == 0 ? 0 : 1 + aP), bP + 1 + cP, bQ + (jQ == 0 ? 0 : 1 + aQ), bQ + 1 + cQ,
-         false);
+      step(bP + (jP == 0 ? 0 : 1 + aP), bP + 1 + cP, bQ + (jQ == 0 ? 0 : 1 + aQ), bQ + 1 + cQ);
       aP = aP == 14 ? 0 : aP + 1;
       cP = cP == 14 ? 0 : cP + 1;
       aQ = aQ == 14 ? 0 : aQ + 1;
