@@ -154,12 +154,13 @@ __device__ inline PairLds pair_lds(double* smem) {
 // current one (branch-free buffer loads, zeros outside the rows and columns).
 // VEC = 0 (the kernel built for two workgroups per CU, which hides latency
 // with the other workgroup and has half the registers): one register set.
+// r0, r1: rows i = lane mod 16 of the two blocks (-1: none).
 template <typename T, int VEC = 1>
-__device__ __forceinline__ void pair_gram(const T* X, int ld, int C, int R, const PairLds& L) {
+__device__ __forceinline__ void pair_gram(const T* X, int ld, int C, int R, const PairLds& L,
+                                          int r0, int r1) {
   typedef typename AccT<T>::type acc_t;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
-  const int r0 = L.rows[i], r1 = L.rows[16 + i];
   const rsrc_t rs = make_rsrc(X, (size_t)R * ld * sizeof(T));
   const uint32_t base0 = r0 >= 0 ? uint32_t(r0) * uint32_t(ld) * uint32_t(sizeof(T)) : OOB;
   const uint32_t base1 = r1 >= 0 ? uint32_t(r1) * uint32_t(ld) * uint32_t(sizeof(T)) : OOB;
@@ -288,11 +289,7 @@ __device__ inline void jacobi_cs(double gpp, double gqq, double gpq,
 
 // v moved down by one lane inside each row of 16 lanes: lane l takes the
 // value of lane 16 (l / 16) + (l + 1) % 16 (DPP row rotate right by 15).
-__device__ __forceinline__ double row_next(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x12F, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x12F, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
+__device__ __forceinline__ double row_next(double v) { return dpp_f64<0x12F>(v); }
 
 // One cyclic parallel Jacobi sweep on the 32x32 symmetric Gram in Ga
 // (float64, LDS), cross-block steps first (both blocks enter with nearly
@@ -401,7 +398,7 @@ __device__ __forceinline__ void gram_sweep32(const PairLds& L, double*& Ga, doub
         worst = fmaxf(worst, (q == q) ? float(q) : 1.0f);
       }
     }
-    for (int o = 32; o > 0; o >>= 1) worst = fmaxf(worst, __shfl_xor(worst, o, 64));
+    worst = wave_max(worst);
     if ((tid & 63) == 0 && worst > float(skip_tol)) L.flag[0] = 1;
     __syncthreads();
     const int need = L.flag[0];
@@ -437,8 +434,8 @@ __device__ const double* inner_eigh(const PairLds& L, bool cross_only, double sk
     const int u = e >> 5, v = e & 31;
     L.Qs[u * GLD + v] = (u == v) ? 1.0 : 0.0;
   }
-  double dmax = 0.0;
-  for (int u = 0; u < 32; ++u) dmax = fmax(dmax, L.Gs[u * GLD + u]);
+  const int lane = tid & 63;
+  const double dmax = wave_max(lane < 32 ? L.Gs[lane * GLD + lane] : 0.0);
   const double floor_abs = 1e-30 * dmax;
   double* Ga = L.Gs;
   double* Gb = L.Gp;          // 32 x GLD, free once the Gram is reduced
@@ -584,31 +581,33 @@ __device__ __forceinline__ void pair_rotate(T* M, int ld, int ncols, int nrows, 
 }
 
 // Global row of pair row tid (< 32) of the visit of blocks I, J: rows are
-// numbered in the sweep's order (fixed for the sweep), -1 past the end.
-__device__ inline int pair_row(const int* order, int I, int J, int nb, int R) {
-  const int tid = threadIdx.x;
-  if (tid >= 32) return -1;
-  const int blk = tid < 16 ? I : J;
-  const int r = blk * BW + (tid & 15);
-  return (blk < nb && r < R) ? load1(order + r) : -1;
+// numbered in the sweep's order (fixed for the sweep), -1 past the end:
+// r0 = row (lane mod 16) of block I, r1 = the same row of block J.
+__device__ inline void pair_rows(const int* order, int I, int J, int nb, int R, int& r0,
+                                 int& r1) {
+  const int i = threadIdx.x & 15;
+  const int a = I * BW + i, b = J * BW + i;
+  r0 = (I < nb && a < R) ? load1(order + a) : -1;
+  r1 = (J < nb && b < R) ? load1(order + b) : -1;
 }
 
 // One pair step of sweep `sw`: Gram, convergence test, inner solve, rotate.
-// prow: pair_row of this thread, loaded before the wait for the blocks.
+// r0, r1: pair_rows of this thread, loaded before the wait for the blocks
+// (which ends with workgroup barriers, so the LDS of the previous visit is
+// free here).
 template <typename T, int VEC = 1>
 __device__ __forceinline__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, int C, int I,
                             int J, int nb, int sw, double F2, double* smem,
                             bool timed, Group& grp,
                             int* verX, int* verW, int target, bool last_round,
-                            bool cross_only, bool forced, int prow) {
+                            bool cross_only, bool forced, int r0, int r1) {
   const PairLds L = pair_lds(smem);
   const int tid = threadIdx.x;
   PhaseClock clk(timed && s.prof != nullptr);
-  __syncthreads();
-  if (tid < 32) L.rows[tid] = prow;
+  // read after the barriers of pair_gram
+  if (tid < 32) L.rows[tid] = tid < 16 ? r0 : r1;
   if (tid == 0) L.flag[1] = 0;
-  __syncthreads();
-  pair_gram<T, VEC>(X, C, C, R, L);
+  pair_gram<T, VEC>(X, C, C, R, L, r0, r1);
   clk.lap(s.prof, PF_GRAM);
   int go = 1;
   const double tol = jacobi_threshold<T>(s, C);
@@ -627,7 +626,7 @@ __device__ __forceinline__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, in
       const double q = den > 0.0 ? guv * __builtin_amdgcn_rcp(den) : (guv > 0.0 ? 1.0 : 0.0);
       worst = fmaxf(worst, (q == q) ? float(q) : 1.0f);
     }
-    for (int o = 32; o > 0; o >>= 1) worst = fmaxf(worst, __shfl_xor(worst, o, 64));
+    worst = wave_max(worst);
     const int need = worst > float(tol);
     if ((tid & 63) == 0 && worst > 0.f)
       atomicMax(&s.ctr[CT_OFFMAX], __float_as_int(worst));
@@ -781,7 +780,8 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
         const int I = tourney_block(q, t, nbe);
         const int J = tourney_block(nbe - 1 - q, t, nbe);
         // the row order is fixed for the sweep: its load overlaps the wait
-        const int prow = pair_row(s.perm, I, J, nb, R);
+        int r0, r1;
+        pair_rows(s.perm, I, J, nb, R, r0, r1);
         PhaseClock wclk(s.prof != nullptr);
         if (!blocks_wait(grp, ver, I, J, base + t)) return false;
         if (wclk.on) {
@@ -792,7 +792,7 @@ __device__ __forceinline__ bool phase_jacobi(const Slot& s, T* X, T* W, int R, i
           }
         }
         if (!jacobi_pair<T, VEC>(s, X, W, R, C, I, J, nb, sw, F2, smem, g == 0, grp, ver, wver, base + t, t == rounds - 1, cross_only, forced,
-                            prow))
+                            r0, r1))
           return false;
       }
     }
