@@ -1124,7 +1124,7 @@ __device__ __forceinline__ void band_eigh(const PairLds& L, int nb, double* Vout
         worst = fmax(worst, d);
       }
     }
-    for (int o = 32; o > 0; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o, 64));
+    worst = wave_max(worst);
     __syncthreads();
     if ((tid & 63) == 0) red[tid >> 6] = worst;
     __syncthreads();
@@ -1224,20 +1224,31 @@ __device__ __forceinline__ int refine_gate(const Slot& s, int k, bool ltr, int R
   if (hi > 0 && lo > 0) {
     double* V = B;                                    // 32 x 32
     if (g == 0) {
+      // the band's Gram (rows b0 .. b0 + nb - 1 of Y; zero past nb): on FP64
+      // MFMA in the FP64 path; in the mixed path by the dot products and wave
+      // sums it has always used, whose summation order its validated results
+      // depend on (a float64 rounding change there moves later float32
+      // Jacobi roundings, and the n=50 job's error by up to 20 %)
       const PairLds L = pair_lds(smem);
-      for (int e = threadIdx.x; e < 32 * 32; e += NT) L.Gs[(e >> 5) * GLD + (e & 31)] = 0.0;
-      __syncthreads();
-      for (int uv = w; uv < nb * nb; uv += 4) {
-        const int u = uv / nb, v = uv - u * nb;
-        if (v < u) continue;
-        double acc = 0.0;
-        const double* yu = Y + (size_t)(b0 + u) * Rr;
-        const double* yv = Y + (size_t)(b0 + v) * Rr;
-        for (int c = lane; c < Rr; c += 64) acc = fma(yu[c], yv[c], acc);
-        acc = wave_sum(acc);
-        if (lane == 0) { L.Gs[u * GLD + v] = acc; L.Gs[v * GLD + u] = acc; }
+      if constexpr (sizeof(T) == 8) {
+        const int i16 = lane & 15;
+        pair_gram<double, 0>(Y, Rr, Rr, rr, L, i16 < nb ? b0 + i16 : -1,
+                             16 + i16 < nb ? b0 + 16 + i16 : -1);
+      } else {
+        for (int e = threadIdx.x; e < 32 * 32; e += NT) L.Gs[(e >> 5) * GLD + (e & 31)] = 0.0;
+        __syncthreads();
+        for (int uv = w; uv < nb * nb; uv += 4) {
+          const int u = uv / nb, v = uv - u * nb;
+          if (v < u) continue;
+          double acc = 0.0;
+          const double* yu = Y + (size_t)(b0 + u) * Rr;
+          const double* yv = Y + (size_t)(b0 + v) * Rr;
+          for (int c = lane; c < Rr; c += 64) acc = fma(yu[c], yv[c], acc);
+          acc = wave_sum(acc);
+          if (lane == 0) { L.Gs[u * GLD + v] = acc; L.Gs[v * GLD + u] = acc; }
+        }
+        __syncthreads();
       }
-      __syncthreads();
       double* EV = V + 1024;
       band_eigh(L, nb, V, EV);
       // the truncation rule again where float64 values decide it: the tie
