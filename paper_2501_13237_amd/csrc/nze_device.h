@@ -340,7 +340,10 @@ __device__ inline bool blocks_wait(Group& grp, const int* ver, int I, int J,
   }
   __syncthreads();
   const int ok = *grp.sflag;
-  __syncthreads();
+  // after a successful wait the next write of sflag follows the barriers of
+  // the visit (or of blocks_release); a failed one returns through paths
+  // without them
+  if (!ok) __syncthreads();
   return ok != 0;
 }
 

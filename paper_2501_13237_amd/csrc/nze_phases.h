@@ -319,7 +319,7 @@ __device__ __forceinline__ double row_next(double v) { return dpp_f64<0x12F>(v);
 __device__ __forceinline__ void gram_sweep32(const PairLds& L, double*& Ga, double*& Gb,
                                              double floor_abs, bool cross_only,
                                              double skip_tol = 0.0, double ratio_abs = 0.0,
-                                             double F2 = 0.0) {
+                                             double F2 = 0.0, bool q_identity = false) {
   const int tid = threadIdx.x;
   if (tid == 0) L.flag[0] = 0;   // ordered by the barrier of the first step
   const int P = tid >> 4, P2 = tid & 15, u0 = 2 * P;
@@ -351,8 +351,14 @@ __device__ __forceinline__ void gram_sweep32(const PairLds& L, double*& Ga, doub
   // 16 + (k + st) mod 16 of J (all 256 cross pairs) ...  (the arithmetic of
   // step(), with the entries that stay on a thread in registers)
   {
-    double qa = L.Qs[u0 * GLD + P2], qb = L.Qs[u0 * GLD + 16 + P2];
-    double qc = L.Qs[(u0 + 1) * GLD + P2], qd = L.Qs[(u0 + 1) * GLD + 16 + P2];
+    double qa, qb, qc, qd;
+    if (q_identity) {
+      qa = u0 == P2 ? 1.0 : 0.0; qb = u0 == 16 + P2 ? 1.0 : 0.0;
+      qc = u0 + 1 == P2 ? 1.0 : 0.0; qd = u0 + 1 == 16 + P2 ? 1.0 : 0.0;
+    } else {
+      qa = L.Qs[u0 * GLD + P2]; qb = L.Qs[u0 * GLD + 16 + P2];
+      qc = L.Qs[(u0 + 1) * GLD + P2]; qd = L.Qs[(u0 + 1) * GLD + 16 + P2];
+    }
     double g11 = Ga[P * GLD + P2], g12 = Ga[P * GLD + 16 + P2];
     const bool piv11 = P == P2, piv12 = P2 == ((P + 1) & 15);
     for (int st = 0; st < 16; ++st) {
@@ -427,20 +433,16 @@ __device__ __forceinline__ void gram_sweep32(const PairLds& L, double*& Ga, doub
 // Qs = I, its intra-block steps skipped when those entries already pass the
 // visit's convergence test (skip_tol = the test's threshold).  Returns the
 // buffer that holds the rotated Gram Q^T G Q.
+// The Gram is complete and Gp free after the barriers of pair_gram and the
+// convergence test; Qs starts as the identity inside gram_sweep32.
 __device__ const double* inner_eigh(const PairLds& L, bool cross_only, double skip_tol,
                                    double ratio_abs, double F2) {
-  const int tid = threadIdx.x;
-  for (int e = tid; e < 32 * 32; e += NT) {
-    const int u = e >> 5, v = e & 31;
-    L.Qs[u * GLD + v] = (u == v) ? 1.0 : 0.0;
-  }
-  const int lane = tid & 63;
+  const int lane = threadIdx.x & 63;
   const double dmax = wave_max(lane < 32 ? L.Gs[lane * GLD + lane] : 0.0);
   const double floor_abs = 1e-30 * dmax;
   double* Ga = L.Gs;
   double* Gb = L.Gp;          // 32 x GLD, free once the Gram is reduced
-  __syncthreads();
-  gram_sweep32(L, Ga, Gb, floor_abs, cross_only, skip_tol, ratio_abs, F2);
+  gram_sweep32(L, Ga, Gb, floor_abs, cross_only, skip_tol, ratio_abs, F2, true);
   return Ga;   // the rotated Gram Q^T G Q
 }
 
@@ -632,8 +634,7 @@ __device__ __forceinline__ bool jacobi_pair(const Slot& s, T* X, T* W, int R, in
       atomicMax(&s.ctr[CT_OFFMAX], __float_as_int(worst));
     if (need) L.flag[1] = 1;
     __syncthreads();
-    go = L.flag[1];
-    __syncthreads();
+    go = L.flag[1];   // rewritten only after later barriers
   }
   clk.lap(s.prof, PF_CHECK);
   const double* Gfin = L.Gs;
