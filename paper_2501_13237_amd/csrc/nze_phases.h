@@ -407,8 +407,7 @@ __device__ __forceinline__ void gram_sweep32(const PairLds& L, double*& Ga, doub
     worst = wave_max(worst);
     if ((tid & 63) == 0 && worst > float(skip_tol)) L.flag[0] = 1;
     __syncthreads();
-    const int need = L.flag[0];
-    __syncthreads();
+    const int need = L.flag[0];   // rewritten only after later barriers
     if (!need) return;
   }
   {
