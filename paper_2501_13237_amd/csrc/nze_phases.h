@@ -1223,29 +1223,36 @@ __device__ __forceinline__ int refine_gate(const Slot& s, int k, bool ltr, int R
   const int nb = lo + hi, b0 = r - lo;
   if (hi > 0 && lo > 0) {
     double* V = B;                                    // 32 x 32
+    // the band's Gram (rows b0 .. b0 + nb - 1 of Y; zero past nb): on FP64
+    // MFMA in the FP64 path; in the mixed path by the dot products and wave
+    // sums it has always used, whose summation order its validated results
+    // depend on (a float64 rounding change there moves later float32 Jacobi
+    // roundings, and the n=50 job's error by up to 20 %), spread over every
+    // wave of the group and gathered in V (band_eigh overwrites V only after
+    // reading the Gram from LDS)
+    if constexpr (sizeof(T) == 4) {
+      for (int uv = g * 4 + w; uv < nb * nb; uv += 4 * G) {
+        const int u = uv / nb, v = uv - u * nb;
+        if (v < u) continue;
+        double acc = 0.0;
+        const double* yu = Y + (size_t)(b0 + u) * Rr;
+        const double* yv = Y + (size_t)(b0 + v) * Rr;
+        for (int c = lane; c < Rr; c += 64) acc = fma(yu[c], yv[c], acc);
+        acc = wave_sum(acc);
+        if (lane == 0) { V[u * 32 + v] = acc; V[v * 32 + u] = acc; }
+      }
+      if (!group_sync(grp)) return 0;
+    }
     if (g == 0) {
-      // the band's Gram (rows b0 .. b0 + nb - 1 of Y; zero past nb): on FP64
-      // MFMA in the FP64 path; in the mixed path by the dot products and wave
-      // sums it has always used, whose summation order its validated results
-      // depend on (a float64 rounding change there moves later float32
-      // Jacobi roundings, and the n=50 job's error by up to 20 %)
       const PairLds L = pair_lds(smem);
       if constexpr (sizeof(T) == 8) {
         const int i16 = lane & 15;
         pair_gram<double, 0>(Y, Rr, Rr, rr, L, i16 < nb ? b0 + i16 : -1,
                              16 + i16 < nb ? b0 + 16 + i16 : -1);
       } else {
-        for (int e = threadIdx.x; e < 32 * 32; e += NT) L.Gs[(e >> 5) * GLD + (e & 31)] = 0.0;
-        __syncthreads();
-        for (int uv = w; uv < nb * nb; uv += 4) {
-          const int u = uv / nb, v = uv - u * nb;
-          if (v < u) continue;
-          double acc = 0.0;
-          const double* yu = Y + (size_t)(b0 + u) * Rr;
-          const double* yv = Y + (size_t)(b0 + v) * Rr;
-          for (int c = lane; c < Rr; c += 64) acc = fma(yu[c], yv[c], acc);
-          acc = wave_sum(acc);
-          if (lane == 0) { L.Gs[u * GLD + v] = acc; L.Gs[v * GLD + u] = acc; }
+        for (int e = threadIdx.x; e < 32 * 32; e += NT) {
+          const int u = e >> 5, v = e & 31;
+          L.Gs[u * GLD + v] = (u < nb && v < nb) ? V[u * 32 + v] : 0.0;
         }
         __syncthreads();
       }
