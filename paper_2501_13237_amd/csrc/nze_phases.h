@@ -310,7 +310,8 @@ __device__ __forceinline__ double row_next(double v) { return dpp_f64<0x12F>(v);
 // the next step's pivots (G[P][P] and G[P][J] of pair P + 1), and all of G
 // and Qs after the last of these steps.  With cross_only the sweep stops
 // after the 16 cross-block steps.  Pivots with |g_pq| <= floor_abs are
-// not rotated.
+// not rotated.  q_identity: Qs starts as the identity (taken in registers;
+// Qs in LDS need not be filled), else from the Qs in LDS.
 // skip_tol > 0: after the cross-block steps, the intra-block steps run only
 // if some intra-block entry fails the visit's convergence test
 // (|g_uv| > skip_tol (sqrt(g_uu g_vv) + ratio_abs sqrt(F2 max(g_uu, g_vv))));
