@@ -316,9 +316,11 @@ __device__ inline bool blocks_wait(Group& grp, const int* ver, int I, int J,
                                    int target) {
   if (threadIdx.x == 0) {
     int ok = 1;
+    // both counters are loaded together (one round trip to L2, not two)
     auto ready = [&]() {
-      return __hip_atomic_load(ver + I, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target &&
-             __hip_atomic_load(ver + J, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target;
+      const int vi = __hip_atomic_load(ver + I, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int vj = __hip_atomic_load(ver + J, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return (vi >= target) & (vj >= target);
     };
     if (!ready()) {
       const uint64_t t0 = wall_clock64();
